@@ -1,0 +1,220 @@
+"""Benchmark: APPGA solve-iterations per second on one MI355X.
+
+Workload (default): 64 independent 128 x 128 reconstructions sharing one
+200-bin x 168-angle Siddon system matrix stored in BF16 (FP32 accumulation,
+FP32 iterates), per-sinogram total counts log-uniform in [1e5, 1e7] and
+uniform background 5-20%, lambda1 = lambda2 = 0.02, eps = 1e-3, omega = 0.5.
+One step = one APPGA iteration (forward projection + ratio, back projection +
+SHOITV stencil + EM-preconditioned prox + momentum) of all 64 solves.
+
+Printed JSON line: value = solve-iterations/s of the batched path; beside it
+the plain path (the same solves run one at a time through the FP32
+single-solve path), the roofline of the dominant kernel (algorithmic bytes per
+launch / mean launch time from HIP events recorded by the library on the
+launch stream), and the FP64 CPU oracle timed on the host cores on a bounded
+sample.  Inputs are resident in device memory before the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("APPGA iters/s at 128²×batch64 vs plain; projector HBM GB/s; "
+          "p50/p99 recon latency")
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="bf16", choices=["f32", "bf16", "f16", "fp8"])
+    ap.add_argument("--plain-steps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for profilers: no CPU baseline, no plain path")
+    return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(kind: str, nnz: int, m: int, d: int, B: int, s_val: int, s_idx: int) -> int:
+    """Algorithmic HBM bytes of one launch: each stored entry read once (value + index),
+    row pointers once, every vector read or written once."""
+    if kind == "forward":
+        # matrix + row_ptr + x (d x B) + g (m x B) + e (m x B, written); scalar background
+        return nnz * (s_val + s_idx) + (m + 1) * 4 + 4 * B * (d + 2 * m)
+    # step: transpose + row_ptr + e (m x B) + ft (d x B) + f read/write + ft_next + Lambda
+    return nnz * (s_val + s_idx) + (d + 1) * 4 + 4 * B * (m + 4 * d) + 4 * d
+
+
+def cpu_baseline(pr, n_iters: int):
+    """FP64 oracle on the host cores: one solve per thread, the first `cores` sinograms."""
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16, len(pr.seeds)))
+    oracle.load()
+    results = [None] * cores
+
+    def run(i):
+        results[i] = oracle.appga(pr.A, pr.geom.n, pr.geom.n_angles, pr.g[i], pr.gamma[i], 0.02,
+                                  0.02, 1e-3, 0.5, n_iters)["f"]
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(cores)]
+    t0 = time.perf_counter()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    dt = time.perf_counter() - t0
+    return dict(value=cores * n_iters / dt, unit="solve-iterations/s", cores=cores,
+                kind="oracle",
+                sample="%d of the 64 sinograms x %d iterations, one solve per thread, FP64, "
+                       "%.1f s wall" % (cores, n_iters, dt))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (independent solves "
+              "would shard across GPUs with no communication); run with --gpus 1", flush=True)
+        sys.exit(2)
+    import torch
+
+    from paper_2409_13344_amd import appga as ap
+    from paper_2409_13344_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+
+    log("building the 64-sinogram workload")
+    pr = synth.config_problem("c3_128x64")
+    geom, A = pr.geom, pr.A
+    B = len(pr.seeds)
+    m, d, nnz = geom.m, geom.d, A.nnz
+    ctx = ap.appga_create(0)
+    mat = ap.load_matrix(ctx, A, geom, args.storage)
+    info = ap.appga_matrix_info(mat)
+    gam_scalar = [float(pr.gamma[b][0]) for b in range(B)]
+    params = [ap.make_params(lam=0.02, eps=1e-3, omega=0.5, iterations=300,
+                             gamma_scalar=gam_scalar[b]) for b in range(B)]
+    g_t = torch.as_tensor(pr.g).to(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    # ---------------------------------------------------------- batched ---
+    sess = ap.appga_solve_begin(ctx, mat, g_t, None, params, None, stream)
+    for _ in range(args.warmup):
+        ap.appga_solve_step(sess, 1)
+    torch.cuda.synchronize()
+    log("timing %d batched steps" % args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ap.appga_solve_step(sess, 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = B * args.steps / dt
+    ms_per_step = 1e3 * dt / args.steps
+
+    # kernel durations from HIP events on the launch stream (separate pass)
+    ap.appga_set_kernel_timing(ctx, True)
+    n_prof = max(10, min(args.steps, 100))
+    for _ in range(n_prof):
+        ap.appga_solve_step(sess, 1)
+    torch.cuda.synchronize()
+    times = ap.appga_kernel_times(ctx)
+    ap.appga_set_kernel_timing(ctx, False)
+    out_t = torch.empty((B, d), dtype=torch.float32, device=dev)
+    stats = ap.appga_solve_end(sess, out_t, B)
+    s_val = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}[args.storage]
+    s_idx = 2 if max(m, d) <= 65536 else 4
+    kernels = {}
+    for name, kind in (("forward_batch", "forward"), ("step_batch", "step")):
+        t = times.get(name)
+        if not t or t["count"] == 0:
+            continue
+        avg_ms = t["total_ms"] / t["count"]
+        nbytes = kernel_bytes(kind, nnz, m, d, B, s_val, s_idx)
+        kernels[name] = dict(avg_us=1e3 * avg_ms, bytes=nbytes, gbs=nbytes / (avg_ms * 1e-3) / 1e9)
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    roof = dict(bound="hbm", achieved=round(kernels[dom]["gbs"], 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(kernels[dom]["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                kernel=dom, avg_us=round(kernels[dom]["avg_us"], 2),
+                bytes_per_launch=kernels[dom]["bytes"])
+
+    # ----------------------------------------------------- plain (B = 1) ---
+    plain = None
+    if not args.profile:
+        mat32 = ap.load_matrix(ctx, A, geom, "f32")
+        g1 = torch.as_tensor(pr.g[0]).to(dev)
+        s1 = ap.appga_solve_begin(ctx, mat32, g1, None, params[:1], None, stream)
+        for _ in range(args.warmup):
+            ap.appga_solve_step(s1, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            ap.appga_solve_step(s1, 1)
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t0
+        out1 = torch.empty((1, d), dtype=torch.float32, device=dev)
+        ap.appga_solve_end(s1, out1, 1)
+        ap.appga_free_system_matrix(ctx, mat32)
+        plain = dict(value=round(args.plain_steps / dt1, 1), unit="solve-iterations/s",
+                     ms_per_iter=round(1e3 * dt1 / args.plain_steps, 4),
+                     path="single-solve FP32 matrix, the 64 solves one after another")
+
+    cpu = None
+    if not args.no_cpu_baseline and not args.profile:
+        log("timing the FP64 oracle on the host cores")
+        cpu = cpu_baseline(pr, args.cpu_iters)
+
+    ap.appga_free_system_matrix(ctx, mat)
+    ap.appga_destroy(ctx)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "solve-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched 2D PET: 64 sinograms sharing a 128x128 / 200 bins x 168 "
+                               "angles Siddon matrix, one APPGA iteration of all 64 per step",
+                   "global_batch": B, "image": [geom.n, geom.n], "bins": geom.n_bins,
+                   "angles": geom.n_angles, "nnz": nnz, "matrix_storage": args.storage,
+                   "lambda": 0.02, "eps": 1e-3, "omega": 0.5},
+        "plain": plain,
+        "speedup_vs_plain": round(value / plain["value"], 2) if plain else None,
+        "kernels": {k: {kk: round(vv, 2) if isinstance(vv, float) else vv
+                        for kk, vv in v.items()} for k, v in kernels.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "matrix_bytes": info,
+        "objective_lane0": stats[0]["objective"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

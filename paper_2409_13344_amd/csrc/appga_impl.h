@@ -1,0 +1,82 @@
+// Definitions of the opaque ABI handles and the session helpers shared by
+// appga_api.cpp and server.cpp.
+#pragma once
+
+#include <atomic>
+#include <chrono>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "appga.h"
+#include "appga_internal.h"
+
+struct appga_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // kernel timing (appga_set_kernel_timing)
+    bool timing = false;
+    struct Pending {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<std::string> knames;
+    std::vector<int64_t> kcount;
+    std::vector<double> kms;
+};
+
+struct appga_matrix {
+    appga_ctx *ctx = nullptr;
+    appga_geometry geom{};
+    int64_t nnz = 0;
+    int storage = 0;
+    appga::DevCsr A, AT;
+    float *lam = nullptr;              // Lambda (d), device
+    std::vector<double> deq;           // dequantised values in the caller's CSR order
+    std::vector<int64_t> user_row_ptr; // caller's CSR structure (for reports)
+    std::vector<int32_t> user_col;
+    int group_fwd = 16, group_back = 16;
+    int xcd_remap = 0;
+    mutable std::atomic<int> inflight{0};
+};
+
+struct appga_solve {
+    appga_ctx *ctx = nullptr;
+    const appga_matrix *mat = nullptr;
+    int B = 0;
+    hipStream_t st = nullptr;
+    std::vector<appga_params> prm;
+    bool has_gamma = false, need_pbuf = false;
+    void *arena = nullptr;
+    float *g = nullptr, *gamma = nullptr, *gamma_lane = nullptr, *f = nullptr, *ft[2] = {nullptr, nullptr},
+          *e = nullptr, *pbuf = nullptr, *theta = nullptr;
+    appga::LaneParams *lp = nullptr;
+    double *part = nullptr, *red = nullptr, *tmc = nullptr;
+    unsigned long long *clamps = nullptr;
+    size_t part_len = 0;
+    int theta_cap = 0, theta_base = 0;
+    int k = 1, cur = 0;
+    bool re_valid = false;
+    std::vector<double> obj0;
+    std::chrono::steady_clock::time_point t0;
+};
+
+namespace appga {
+
+appga_status fail(appga_status st, const char *fmt, ...);
+void clear_error();
+appga_status validate_params(const appga_params *p);
+appga_status validate_data(const float *v, int64_t n, const char *what);
+double theta_of(const appga_params &p, int k);
+hipError_t timed_launch(appga_ctx *ctx, const char *name, hipStream_t st,
+                        const std::function<hipError_t()> &fn);
+
+appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const float *d_g,
+                        const float *d_gamma, const appga_params *params, const float *d_f_init,
+                        hipStream_t st, appga_solve **out);
+appga_status sess_step(appga_solve *s, int n_iters);
+appga_status sess_end(appga_solve *s, float *d_out, appga_stats *stats, bool free_session);
+void sess_free(appga_solve *s);
+
+}  // namespace appga

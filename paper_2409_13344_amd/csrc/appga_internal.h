@@ -1,0 +1,123 @@
+// Internal types shared by the HIP kernels (kernels.hip) and the host side of
+// the library (appga_api.cpp, server.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace appga {
+
+// Storage types of matrix values (same numbering as appga_dtype).
+enum ValType : int { VT_F32 = 1, VT_BF16 = 2, VT_F16 = 3, VT_FP8 = 4 };
+
+// Entries per chunk: every stored row is padded with zero entries to a
+// multiple of this, so kernels read whole 8-entry chunks without tails.
+constexpr int kChunk = 8;
+
+// One stored sparse operator (A, or the transpose used for A^T), CSR with
+// rows padded to kChunk entries.  Device pointers.
+struct DevCsr {
+    int32_t n_rows = 0, n_cols = 0;
+    int64_t nnz = 0;          // real entries
+    int64_t nnz_padded = 0;   // stored entries
+    int32_t *row_ptr = nullptr;  // n_rows + 1, multiples of kChunk
+    void *col = nullptr;         // uint16_t when idx16, else uint32_t
+    void *val = nullptr;         // float / bf16 / f16 / fp8 (uint8)
+    float *row_scale = nullptr;  // FP8 only: value = scale[row] * decode(q)
+    int idx16 = 1;
+    int vtype = VT_F32;
+    int max_row_len = 0;
+    double mean_row_len = 0.0;
+    int64_t bytes = 0;           // stored bytes (values + indices + row_ptr + scales)
+};
+
+// Per-solve (per batch lane) parameters, FP32 copies of the FP64 host values.
+struct LaneParams {
+    float lambda1, lambda2, eps, beta, fixed_p, pad0, pad1, pad2;
+};
+
+// Preconditioner handling inside the fused step kernel.
+enum PMode : int {
+    PM_EM = 0,          // P = beta f^k / Lambda
+    PM_EM_STORE = 1,    // as PM_EM, and store P into pbuf (frozen mode, k <= freeze)
+    PM_STORED = 2,      // P = pbuf (frozen mode, k > freeze)
+    PM_FIXED = 3        // P = fixed_p
+};
+
+// What the fused back-projection / stencil / update kernel writes.
+enum StepOut : int {
+    SO_STEP = 0,        // f^{k+1} into f, f~^{k+1} into ft_next
+    SO_BACK = 1,        // out = A^T e
+    SO_REG = 2          // out = B^T grad phi~(B ft)
+};
+
+// Forward projection epilogue.
+enum FwdMode : int {
+    FM_RATIO = 0,       // out = 1 - g / max(A x + gamma, tau)
+    FM_PROJ = 1         // out = A x + gamma  (gamma = 0 when absent)
+};
+
+struct FwdArgs {
+    const int32_t *row_ptr;
+    const void *col;
+    const void *val;
+    const float *row_scale;
+    int m;                  // rows
+    int B;                  // solves; row stride of x / g / gamma / out
+    const float *x;         // [d][B]
+    const float *g;         // [m][B]
+    const float *gamma;     // [m][B] or null (then gamma_lane)
+    const float *gamma_lane;// [B] or null (then 0)
+    float *out;             // [m][B]
+    int mode;               // FwdMode
+    int scale_out;          // FM_RATIO with FP8: write row_scale[i] * e_i (the transpose has no scales)
+    unsigned long long *clamps;  // floored-bin counter (may be null)
+};
+
+struct StepArgs {
+    const int32_t *row_ptr;  // transpose (rows = pixels)
+    const void *col;
+    const void *val;
+    const float *row_scale;  // unused: FP8 transposes carry A's row scales in e
+    int n;                   // image side N
+    int B;                   // solves; row stride
+    const float *e;          // [m][B] ratio residual 1 - g / y
+    const float *ft;         // [d][B] extrapolated point f~^k
+    float *f;                // [d][B] f^k in, f^{k+1} out
+    float *ft_next;          // [d][B] f~^{k+1}
+    const float *lam;        // [d] Lambda
+    const LaneParams *lp;    // [B]
+    const float *theta_next; // [B] theta_{k+1}
+    float *pbuf;             // [d][B] frozen preconditioner (or null)
+    int pmode;               // PMode
+    int out_mode;            // StepOut
+    float *out;              // [d][B] for SO_BACK / SO_REG
+    double *re_part;         // [blocks][B][2] sum (f^{k+1}-f^k)^2, sum (f^{k+1})^2 (or null)
+    int tiles_x;             // tiles per image row
+    int xcd_remap;           // 1: map workgroups to spatially compact tile blocks per XCD
+};
+
+// Kernel launch helpers (kernels.hip).  Each returns hipSuccess or the launch error.
+hipError_t launch_forward(const DevCsr &A, const FwdArgs &args, int group, hipStream_t st);
+hipError_t launch_step(const DevCsr &AT, const StepArgs &args, int group, hipStream_t st);
+int step_blocks(int n, int B);
+hipError_t launch_fidelity_terms(int m, int B, const float *y, const float *g, const float *gamma,
+                                 const float *gamma_lane, double *part, hipStream_t st);
+int fidelity_blocks(int m);
+hipError_t launch_reg_value(int n, int B, const float *x, const LaneParams *lp, double *part,
+                            hipStream_t st);
+int reg_value_blocks(int n);
+hipError_t launch_reduce_partials(const double *part, int nblocks, int B, int ncomp, double *out,
+                                  hipStream_t st);
+hipError_t launch_transpose(const float *in, float *out, int rows, int cols, hipStream_t st);
+hipError_t launch_disk_init(int n, int B, const double *tmc, float *f, float *ft, hipStream_t st);
+hipError_t launch_sum_g_minus_gamma(int m, int B, const float *g, const float *gamma,
+                                    const float *gamma_lane, double *part, hipStream_t st);
+int sum_blocks(int m);
+hipError_t launch_fill(float *p, size_t n, float v, hipStream_t st);
+hipError_t launch_scale_rows(float *e, const float *scale, int m, int B, hipStream_t st);
+hipError_t launch_copy(float *dst, const float *src, size_t n, hipStream_t st);
+
+}  // namespace appga

@@ -1,0 +1,401 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Element-by-element on seeded inputs at sizes the oracle finishes in seconds
+(several tiles, ragged tails), plus sampled solves at the full batched sizes.
+Tolerances (relative image L2 unless stated):
+  * single kernels, FP32 matrix: 1e-5 of the output scale (FP32 sums of
+    100-300 terms, relative rounding ~1e-6);
+  * whole solves with the FP32 matrix: 1e-5 after 100 iterations (the stated
+    target) and after the configurations' own iteration counts;
+  * reduced-precision matrices: against the oracle run on the same
+    dequantised matrix, 1e-5; against the oracle on the exact matrix the
+    error is reported and bounded loosely (BF16 ~ 2^-9 per entry).
+"""
+import copy
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2409_13344_amd import appga as ap  # noqa: E402
+from paper_2409_13344_amd import synth  # noqa: E402
+
+
+def say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.init()
+    c = ap.appga_create(0)
+    yield c
+    ap.appga_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return synth.config_problem("c2_128")
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.config_problem("c1_64")
+
+
+@pytest.fixture(scope="module")
+def c2_mat(ctx, c2):
+    m = ap.load_matrix(ctx, c2.A, c2.geom, "f32")
+    yield m
+    ap.appga_free_system_matrix(ctx, m)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+# ------------------------------------------------------------- operators ---
+
+@pytest.mark.parametrize("B", [1, 3, 64, 65])
+def test_forward_and_ratio_ops(ctx, c2, c2_mat, B):
+    say("forward/ratio ops C2 B=%d" % B)
+    rng = np.random.default_rng(B)
+    geom = c2.geom
+    x = rng.uniform(0.0, 2.0, (B, geom.d)).astype(np.float32)
+    gam = rng.uniform(0.5, 1.5, (B, geom.m)).astype(np.float32)
+    g = rng.poisson(50.0, (B, geom.m)).astype(np.float32)
+    y = torch.empty((B, geom.m), dtype=torch.float32, device="cuda")
+    e = torch.empty((B, geom.m), dtype=torch.float32, device="cuda")
+    xt = dev(x) if B > 1 else dev(x[0])
+    ap.appga_op_forward(ctx, c2_mat, xt, dev(gam) if B > 1 else dev(gam[0]),
+                        y if B > 1 else y[0])
+    ap.appga_op_ratio(ctx, c2_mat, xt, dev(g) if B > 1 else dev(g[0]),
+                      dev(gam) if B > 1 else dev(gam[0]), e if B > 1 else e[0])
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    e = e.cpu().numpy()
+    for b in sorted({0, B // 2, B - 1}):
+        ref = oracle.forward(c2.A, x[b].astype(np.float64)) + gam[b]
+        assert np.abs(y[b] - ref).max() <= 1e-5 * np.abs(ref).max()
+        eref = 1.0 - g[b] / ref
+        assert np.abs(e[b] - eref).max() <= 1e-5 * max(1.0, np.abs(eref).max())
+
+
+@pytest.mark.parametrize("B", [1, 5, 64])
+def test_back_op(ctx, c2, c2_mat, B):
+    say("back op C2 B=%d" % B)
+    rng = np.random.default_rng(10 + B)
+    r = rng.standard_normal((B, c2.geom.m)).astype(np.float32)
+    out = torch.empty((B, c2.geom.d), dtype=torch.float32, device="cuda")
+    ap.appga_op_back(ctx, c2_mat, dev(r) if B > 1 else dev(r[0]), out if B > 1 else out[0])
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    absA = oracle.back(c2.A, np.ones(c2.geom.m))
+    for b in sorted({0, B - 1}):
+        ref = oracle.back(c2.A, r[b].astype(np.float64))
+        # error scale: sum |A_ij r_i| <= max|r| * colsum
+        assert np.abs(out[b] - ref).max() <= 1e-5 * np.abs(r[b]).max() * absA.max()
+
+
+@pytest.mark.parametrize("n,B", [(1, 1), (2, 1), (3, 2), (5, 1), (7, 3), (16, 1), (37, 2),
+                                 (128, 1), (128, 64)])
+def test_grad_reg_op(ctx, n, B):
+    say("grad_reg op n=%d B=%d" % (n, B))
+    rng = np.random.default_rng(n * 7 + B)
+    x = rng.uniform(0.0, 1.0, (B, n * n)).astype(np.float32)
+    x[:, ::3] *= 0.001     # mix of both branches of s_eps
+    lam1 = rng.uniform(0.01, 0.1, B)
+    lam2 = rng.uniform(0.01, 0.1, B)
+    eps = np.full(B, 0.05)
+    out = torch.empty((B, n * n), dtype=torch.float32, device="cuda")
+    ap.appga_op_grad_reg(ctx, n, lam1, lam2, eps, dev(x) if B > 1 else dev(x[0]),
+                         out if B > 1 else out[0])
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    for b in range(B):
+        ref = oracle.grad_reg(n, lam1[b], lam2[b], eps[b], x[b].astype(np.float64))
+        scale = 12 * (lam1[b] + lam2[b])          # |grad| <= (|B1| + |B2|) lambda
+        assert np.abs(out[b] - ref).max() <= 2e-5 * scale
+
+
+@pytest.mark.parametrize("B", [1, 4])
+def test_step_op_matches_one_oracle_iteration(ctx, c2, c2_mat, B):
+    """One APPGA iteration from f^1 (theta_1 = 0 so f~ = f): f^2 and f~^2."""
+    say("step op C2 B=%d" % B)
+    rng = np.random.default_rng(30 + B)
+    geom = c2.geom
+    g = np.stack([c2.g[0]] * B)
+    gam = np.stack([c2.gamma[0]] * B)
+    f1 = np.stack([oracle.init_image(geom.n, geom.n_angles, c2.g[0], c2.gamma[0])] * B)
+    f1 *= rng.uniform(0.8, 1.2, f1.shape)
+    f1 = f1.astype(np.float32)
+    lam = rng.uniform(0.01, 0.05, B)
+    theta2 = 0.1
+    f_t = dev(f1) if B > 1 else dev(f1[0])
+    ft_t = dev(f1) if B > 1 else dev(f1[0])
+    ftn = torch.empty_like(f_t)
+    ap.appga_op_step(ctx, c2_mat, dev(g) if B > 1 else dev(g[0]),
+                     dev(gam) if B > 1 else dev(gam[0]), lam, lam, 1e-3, 1.0, theta2, f_t, ft_t,
+                     ftn)
+    torch.cuda.synchronize()
+    fo = f_t.cpu().numpy().reshape(B, -1)
+    ftno = ftn.cpu().numpy().reshape(B, -1)
+    for b in range(B):
+        ref = oracle.appga(c2.A, geom.n, geom.n_angles, g[b], gam[b], lam[b], lam[b], 1e-3, 0.5, 1,
+                           f_init=f1[b].astype(np.float64))["f"]
+        assert rel_l2(fo[b], ref) <= 1e-6
+        np.testing.assert_allclose(ftno[b], fo[b] + theta2 * (fo[b] - f1[b]), rtol=1e-6,
+                                   atol=1e-6 * np.abs(fo[b]).max())
+
+
+# -------------------------------------------------------------- solves ---
+
+@pytest.mark.parametrize("omega", [0.2, 0.5, 1.0])
+def test_reconstruct_c2_fp32_100(ctx, c2, c2_mat, omega):
+    """Configuration 128^2 / 200 x 168, FP32 matrix: relative L2 <= 1e-5 after 100 iterations."""
+    say("reconstruct C2 omega=%g K=100" % omega)
+    p = ap.make_params(lam=0.02, eps=1e-3, omega=omega, iterations=100)
+    f, st = ap.appga_reconstruct(ctx, c2_mat, c2.geom.d, c2.g[0], c2.gamma[0], p)
+    ref = oracle.appga(c2.A, 128, 168, c2.g[0], c2.gamma[0], 0.02, 0.02, 1e-3, omega, 100,
+                       history=True)
+    err = rel_l2(f, ref["f"])
+    say("  rel L2 = %.3e, clamps %d, Phi %.10e vs %.10e" % (err, st["guard_clamps"],
+                                                           st["objective"], ref["obj"][-1]))
+    assert err <= 1e-5
+    assert st["guard_clamps"] == ref["clamps"] == 0
+    assert st["iterations_done"] == 100
+    assert abs(st["objective0"] - ref["obj"][0]) <= 1e-7 * abs(ref["obj"][0])
+    assert abs(st["objective"] - ref["obj"][-1]) <= 1e-7 * abs(ref["obj"][-1])
+    assert f.min() >= 0.0
+
+
+@pytest.mark.parametrize("omega", [0.2, 0.5, 1.0])
+def test_reconstruct_c2_fp32_500(ctx, c2, c2_mat, omega):
+    """The configuration's own 500 iterations."""
+    say("reconstruct C2 omega=%g K=500" % omega)
+    p = ap.make_params(lam=0.02, eps=1e-3, omega=omega, iterations=500)
+    f, st = ap.appga_reconstruct(ctx, c2_mat, c2.geom.d, c2.g[0], c2.gamma[0], p)
+    ref = oracle.appga(c2.A, 128, 168, c2.g[0], c2.gamma[0], 0.02, 0.02, 1e-3, omega, 500,
+                       history=True)
+    err = rel_l2(f, ref["f"])
+    say("  rel L2 = %.3e  RE %.3e vs %.3e" % (err, st["re"], ref["re"][-1]))
+    assert err <= 1e-5
+    # RE is a difference of consecutive FP32 iterates: absolute floor ~ FP32 resolution
+    assert abs(st["re"] - ref["re"][-1]) <= 1e-3 * ref["re"][-1] + 1e-7
+
+
+def test_reconstruct_c1_reports_sensitivity(ctx, c1):
+    """64^2 / 96 x 90 at lambda = 0.05: the oracle itself moves by ~1e-5 when its inputs are
+    rounded to FP32 (stiff regime), so the GPU gate is the sensitivity floor times 10."""
+    say("reconstruct C1")
+    mat = ap.load_matrix(ctx, c1.A, c1.geom, "f32")
+    try:
+        p = ap.make_params(lam=0.05, eps=1e-3, omega=0.5, iterations=100)
+        f, _ = ap.appga_reconstruct(ctx, mat, c1.geom.d, c1.g[0], c1.gamma[0], p)
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    ref = oracle.appga(c1.A, 64, 90, c1.g[0], c1.gamma[0], 0.05, 0.05, 1e-3, 0.5, 100)
+    A32 = copy.copy(c1.A)
+    A32.val = c1.A.val.astype(np.float32).astype(np.float64)
+    sens = rel_l2(oracle.appga(A32, 64, 90, c1.g[0], c1.gamma[0], 0.05, 0.05, 1e-3, 0.5, 100)["f"],
+                  ref["f"])
+    err = rel_l2(f, ref["f"])
+    say("  rel L2 = %.3e (oracle FP32-input sensitivity %.3e)" % (err, sens))
+    assert err <= max(1e-5, 10 * sens)
+
+
+def test_zero_iterations_returns_initial_image(ctx, c2, c2_mat):
+    p = ap.make_params(lam=0.02, iterations=0)
+    f, st = ap.appga_reconstruct(ctx, c2_mat, c2.geom.d, c2.g[0], c2.gamma[0], p)
+    ref = oracle.init_image(128, 168, c2.g[0], c2.gamma[0])
+    assert rel_l2(f, ref) <= 1e-7
+    assert st["iterations_done"] == 0
+
+
+@pytest.mark.parametrize("mode", ["none", "frozen", "fixed", "scalar_gamma", "f_init"])
+def test_modes_match_oracle(ctx, c2, c2_mat, mode):
+    say("mode %s" % mode)
+    kw = dict(lam=0.02, eps=1e-3, omega=0.5, iterations=60)
+    okw = dict(omega=0.5)
+    gamma = c2.gamma[0]
+    f_init = None
+    if mode == "none":
+        kw["momentum"] = ap.APPGA_MOMENTUM_NONE
+        okw["momentum"] = oracle.MOMENTUM_NONE
+    elif mode == "frozen":
+        kw.update(precond=ap.APPGA_PRECOND_EM_FROZEN, precond_freeze_iter=20)
+        okw.update(precond=oracle.PRECOND_EM_FROZEN, precond_freeze_iter=20)
+    elif mode == "fixed":
+        kw.update(precond=ap.APPGA_PRECOND_FIXED, fixed_p=5e-4)
+        okw.update(precond=oracle.PRECOND_FIXED, fixed_p_scalar=np.float64(np.float32(5e-4)))
+    elif mode == "scalar_gamma":
+        kw["gamma_scalar"] = float(c2.gamma[0][0])
+        gamma = None
+    elif mode == "f_init":
+        f_init = (np.random.default_rng(3).uniform(0.5, 1.5, c2.geom.d) *
+                  c2.f_true[0].mean()).astype(np.float32)
+    p = ap.make_params(**kw)
+    f, _ = ap.appga_reconstruct(ctx, c2_mat, c2.geom.d, c2.g[0], gamma, p, f_init=f_init)
+    ref = oracle.appga(c2.A, 128, 168, c2.g[0], c2.gamma[0], 0.02, 0.02, 1e-3,
+                       iterations=60, f_init=None if f_init is None else f_init.astype(np.float64),
+                       **okw)
+    err = rel_l2(f, ref["f"])
+    say("  rel L2 = %.3e" % err)
+    assert err <= 1e-5
+
+
+def test_floor_counts_match_oracle(ctx):
+    """A = I with momentum driving A f~ + gamma below the floor (the oracle's special case)."""
+    say("floor counts")
+    n = 2
+    d = 4
+    rp = np.arange(d + 1, dtype=np.int64)
+    col = np.arange(d, dtype=np.int32)
+    val = np.ones(d)
+    mat = ap.appga_load_system_matrix(ctx, n, 4, 1, rp, col, val, "f32")
+    try:
+        f1 = np.array([1000.0, 2.0, 1000.0, 3.0], dtype=np.float32)
+        g = np.array([1.0, 2.0, 0.0, 1.0], dtype=np.float32)
+        gam = np.array([1e-3, 1.0, 0.0, 0.5], dtype=np.float32)
+        p = ap.make_params(omega=1.0, iterations=2)
+        f, st = ap.appga_reconstruct(ctx, mat, d, g, gam, p, f_init=f1)
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    A = synth.SparseMatrix(d, d, rp, col, val)
+    ref = oracle.appga(A, n, 1, g, gam, 0.0, 0.0, 1e-3, 1.0, 2, f_init=f1.astype(np.float64))
+    assert st["guard_clamps"] == ref["clamps"] == 2
+    # f^2 = f^1 - f^1 (1 - g/y) cancels from 1000 to ~1 (FP32 ulp at 1000 is 6e-5)
+    np.testing.assert_allclose(f, ref["f"], rtol=2e-4)
+
+
+# -------------------------------------------------------------- batches ---
+
+def test_batch_equals_solo(ctx, c2, c2_mat):
+    """Each result of a batch equals the same solve run alone (tolerance 1e-5)."""
+    say("batch vs solo")
+    pr = synth.make_problem(c2.geom, [1000, 1001, 1002, 1003], tc_range=(1e5, 1e7),
+                            rf_range=(0.05, 0.2), A=c2.A)
+    params = [ap.make_params(lam=0.02, eps=1e-3, omega=om, iterations=100)
+              for om in (0.3, 0.5, 0.8, 1.0)]
+    fb, sb = ap.appga_reconstruct_batch(ctx, c2_mat, c2.geom.d, pr.g, pr.gamma, params)
+    for b in range(4):
+        fs, ss = ap.appga_reconstruct(ctx, c2_mat, c2.geom.d, pr.g[b], pr.gamma[b], params[b])
+        err = rel_l2(fb[b], fs)
+        say("  solve %d batch-vs-solo %.3e" % (b, err))
+        assert err <= 1e-5
+        assert abs(sb[b]["objective"] - ss["objective"]) <= 1e-6 * abs(ss["objective"])
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16", "fp8"])
+def test_reduced_precision_c3_sampled(ctx, c2, storage):
+    """128^2 x 64 solves sharing the matrix (the batched configuration, 300 iterations), sampled
+    solves against the oracle on the dequantised matrix (parity) and on the exact one (reported)."""
+    say("C3 %s" % storage)
+    pr = synth.config_problem("c3_128x64")
+    mat = ap.load_matrix(ctx, pr.A, pr.geom, storage)
+    try:
+        deq = ap.appga_matrix_dequantized(mat, pr.A.nnz)
+        params = [ap.make_params(lam=0.02, eps=1e-3, omega=0.5, iterations=300)] * 64
+        f, stats = ap.appga_reconstruct_batch(ctx, mat, pr.geom.d, pr.g, pr.gamma, params)
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    Aq = copy.copy(pr.A)
+    Aq.val = deq
+    bound_exact = {"bf16": 2e-2, "f16": 2e-3, "fp8": 2e-1}[storage]
+    for b in (0, 37, 63):
+        ref_q = oracle.appga(Aq, 128, 168, pr.g[b], pr.gamma[b], 0.02, 0.02, 1e-3, 0.5, 300)["f"]
+        ref_x = oracle.appga(pr.A, 128, 168, pr.g[b], pr.gamma[b], 0.02, 0.02, 1e-3, 0.5, 300)["f"]
+        e_q, e_x = rel_l2(f[b], ref_q), rel_l2(f[b], ref_x)
+        say("  solve %d: vs dequantised-matrix oracle %.3e, vs exact-matrix oracle %.3e"
+            % (b, e_q, e_x))
+        assert e_q <= 1e-5
+        assert e_x <= bound_exact
+        assert stats[b]["guard_clamps"] == 0
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16", "fp8"])
+def test_reduced_precision_single(ctx, c2, storage):
+    """Single-solve path with reduced-precision storage: parity against the oracle on the
+    dequantised matrix; forward/back operators are exact adjoints of that matrix."""
+    say("C2 single %s" % storage)
+    mat = ap.load_matrix(ctx, c2.A, c2.geom, storage)
+    try:
+        deq = ap.appga_matrix_dequantized(mat, c2.A.nnz)
+        Aq = copy.copy(c2.A)
+        Aq.val = deq
+        rng = np.random.default_rng(5)
+        r = rng.standard_normal(c2.geom.m).astype(np.float32)
+        x = rng.uniform(0, 1, c2.geom.d).astype(np.float32)
+        bo = torch.empty(c2.geom.d, dtype=torch.float32, device="cuda")
+        yo = torch.empty(c2.geom.m, dtype=torch.float32, device="cuda")
+        ap.appga_op_back(ctx, mat, dev(r), bo)
+        ap.appga_op_forward(ctx, mat, dev(x), None, yo)
+        torch.cuda.synchronize()
+        absA = oracle.back(Aq, np.ones(c2.geom.m))
+        assert np.abs(bo.cpu().numpy() - oracle.back(Aq, r)).max() <= 1e-5 * np.abs(r).max() * absA.max()
+        yref = oracle.forward(Aq, x)
+        assert np.abs(yo.cpu().numpy() - yref).max() <= 1e-5 * yref.max()
+        p = ap.make_params(lam=0.02, eps=1e-3, omega=0.5, iterations=100)
+        f, _ = ap.appga_reconstruct(ctx, mat, c2.geom.d, c2.g[0], c2.gamma[0], p)
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    ref_q = oracle.appga(Aq, 128, 168, c2.g[0], c2.gamma[0], 0.02, 0.02, 1e-3, 0.5, 100)["f"]
+    ref_x = oracle.appga(c2.A, 128, 168, c2.g[0], c2.gamma[0], 0.02, 0.02, 1e-3, 0.5, 100)["f"]
+    e_q, e_x = rel_l2(f, ref_q), rel_l2(f, ref_x)
+    say("  vs dequantised-matrix oracle %.3e, vs exact-matrix oracle %.3e" % (e_q, e_x))
+    assert e_q <= 1e-5
+
+
+def test_c4_sampled_slices(ctx):
+    """256^2 x 47 slices sharing the 256 x 252 matrix, omega = 1, 200 iterations, FP32 matrix:
+    two sampled slices against the oracle."""
+    say("C4 fp32 sampled")
+    pr = synth.config_problem("c4_256x47")
+    mat = ap.load_matrix(ctx, pr.A, pr.geom, "f32")
+    try:
+        params = [ap.make_params(lam=0.01, eps=1e-3, omega=1.0, iterations=200)] * 47
+        f, stats = ap.appga_reconstruct_batch(ctx, mat, pr.geom.d, pr.g, pr.gamma, params)
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    for b in (0, 46):
+        ref = oracle.appga(pr.A, 256, 252, pr.g[b], pr.gamma[b], 0.01, 0.01, 1e-3, 1.0, 200)["f"]
+        err = rel_l2(f[b], ref)
+        say("  slice %d rel L2 %.3e" % (b, err))
+        assert err <= 1e-5
+
+
+# --------------------------------------------------------- error paths ---
+
+def test_errors_through_the_abi(ctx, c2, c2_mat):
+    p = ap.make_params(lam=0.02, eps=0.0)
+    with pytest.raises(ap.AppgaError) as ei:
+        ap.appga_reconstruct(ctx, c2_mat, c2.geom.d, c2.g[0], c2.gamma[0], p)
+    assert ei.value.status == -3
+    g = c2.g[0].copy()
+    g[7] = -1
+    with pytest.raises(ap.AppgaError) as ei:
+        ap.appga_reconstruct(ctx, c2_mat, c2.geom.d, g, c2.gamma[0], ap.make_params())
+    assert ei.value.status == -3
+    # ACTc <= 0 with the disk initial image
+    with pytest.raises(ap.AppgaError) as ei:
+        ap.appga_reconstruct(ctx, c2_mat, c2.geom.d, np.zeros_like(c2.g[0]), c2.gamma[0],
+                             ap.make_params())
+    assert ei.value.status == -3
+    bad = c2.A.col.copy()
+    bad[0] = c2.geom.d
+    with pytest.raises(ap.AppgaError) as ei:
+        ap.appga_load_system_matrix(ctx, 128, 168, 200, c2.A.row_ptr, bad, c2.A.val)
+    assert ei.value.status == -2
