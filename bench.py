@@ -41,9 +41,12 @@ def parse():
     ap.add_argument("--storage", default="bf16", choices=["f32", "bf16", "f16", "fp8"])
     ap.add_argument("--plain-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--cpu-iters", type=int, default=300)
     ap.add_argument("--profile", action="store_true",
                     help="short run for profilers: no CPU baseline, no plain path")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also launch a plain device copy of MIB MiB (5 times) so that a "
+                         "profiler's FETCH_SIZE/WRITE_SIZE can be scaled by a known size")
     return ap.parse_args()
 
 
@@ -103,6 +106,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.init()
     dev = torch.device("cuda:0")
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 5 copies of %d MiB" % args.calibrate_copy)
+        del src, dst
 
     log("building the 64-sinogram workload")
     pr = synth.config_problem("c3_128x64")

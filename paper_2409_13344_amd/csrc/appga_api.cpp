@@ -260,6 +260,7 @@ struct HostPacked {
     std::vector<int32_t> row_ptr;
     std::vector<uint16_t> col16;
     std::vector<uint32_t> col32;
+    std::vector<uint32_t> col32u;   // col * 256: byte offset of a column's 64-lane record (B > 1)
     std::vector<uint8_t> val;  // raw bytes of the stored values
     std::vector<float> scale;
     int max_len = 0;
@@ -294,15 +295,17 @@ appga_status pack_rows(int64_t nrows, int64_t ncols, const int64_t *rp, const in
     for (int64_t i = 0; i < nrows; ++i) {
         const int64_t len = rp[i + 1] - rp[i];
         hp.max_len = std::max<int64_t>(hp.max_len, len);
-        total += (len + kChunk - 1) / kChunk * kChunk;
+        total += (len + kRowPad - 1) / kRowPad * kRowPad;
         if (total > 0x7FFFFFF0LL) return fail(APPGA_E_SHAPE, "too many stored entries (>= 2^31)");
         hp.row_ptr[i + 1] = static_cast<int32_t>(total);
     }
     const bool idx16 = ncols <= 65536;
+    if (ncols > (1LL << 24)) return fail(APPGA_E_SHAPE, "too many columns for 32-bit lane offsets");
     if (idx16)
         hp.col16.assign(total, 0);
     else
         hp.col32.assign(total, 0);
+    hp.col32u.assign(total, 0);
     const size_t vsz = vtype == VT_F32 ? 4 : (vtype == VT_FP8 ? 1 : 2);
     hp.val.assign(total * vsz, 0);
     if (vtype == VT_FP8 && scales) hp.scale.assign(scales, scales + nrows);
@@ -319,6 +322,7 @@ appga_status pack_rows(int64_t nrows, int64_t ncols, const int64_t *rp, const in
                 hp.col16[o + t] = static_cast<uint16_t>(c);
             else
                 hp.col32[o + t] = c;
+            hp.col32u[o + t] = c * 256u;
             double dq = 0.0;
             uint8_t *dst = hp.val.data() + (o + t) * vsz;
             switch (vtype) {
@@ -380,6 +384,8 @@ appga_status to_device(const HostPacked &hp, int64_t nrows, int64_t ncols, int64
     else
         ST_TRY(upload(hp.col32, &dc.col, dc.bytes));
     ST_TRY(upload(hp.val, &dc.val, dc.bytes));
+    int64_t off_bytes = 0;  // the lane-record offsets are a second index array, counted apart
+    ST_TRY(upload(hp.col32u, reinterpret_cast<void **>(&dc.col32), off_bytes));
     ST_TRY(upload(hp.scale, reinterpret_cast<void **>(&dc.row_scale), dc.bytes));
     return APPGA_OK;
 }
@@ -387,6 +393,7 @@ appga_status to_device(const HostPacked &hp, int64_t nrows, int64_t ncols, int64
 void free_csr(DevCsr &dc) {
     hipFree(dc.row_ptr);
     hipFree(dc.col);
+    hipFree(dc.col32);
     hipFree(dc.val);
     hipFree(dc.row_scale);
     dc = DevCsr();
@@ -529,6 +536,7 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
     }
     mat->group_fwd = env_int("APPGA_GROUP_FWD", plan_group(mat->A.mean_row_len));
     mat->group_back = env_int("APPGA_GROUP_BACK", plan_group(mat->AT.mean_row_len));
+    mat->fwd_wgs = env_int("APPGA_FWD_WGS", 2048);
     // the remap needs the tile grid (tx x tx) to split into 2 x 4 equal blocks
     const int tx = (geom->n + 3) / 4;
     const bool remap_ok = tx % 4 == 0;
@@ -630,28 +638,30 @@ static appga_status sess_alloc(appga_solve *s) {
     const int sb = step_blocks(s->mat->geom.n, B);
     const int nb = std::max({fidelity_blocks(static_cast<int>(m)), reg_value_blocks(s->mat->geom.n),
                              sum_blocks(static_cast<int>(m)), sb});
-    s->part_len = static_cast<size_t>(nb) * B * 2;
+    const int Bp = pad_lanes(B);
+    s->Bp = Bp;
+    s->part_len = static_cast<size_t>(nb) * Bp * 2;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
         off += (bytes + 255) / 256 * 256;
         return o;
     };
-    const size_t o_g = take(sizeof(float) * m * B);
-    const size_t o_gam = s->has_gamma ? take(sizeof(float) * m * B) : 0;
-    const size_t o_gl = take(sizeof(float) * B);
-    const size_t o_f = take(sizeof(float) * d * B);
-    const size_t o_ft0 = take(sizeof(float) * d * B);
-    const size_t o_ft1 = take(sizeof(float) * d * B);
-    const size_t o_e = take(sizeof(float) * m * B);
-    const size_t o_pb = s->need_pbuf ? take(sizeof(float) * d * B) : 0;
-    const size_t o_lp = take(sizeof(LaneParams) * B);
+    const size_t o_g = take(sizeof(float) * m * Bp);
+    const size_t o_gam = s->has_gamma ? take(sizeof(float) * m * Bp) : 0;
+    const size_t o_gl = take(sizeof(float) * Bp);
+    const size_t o_f = take(sizeof(float) * d * Bp);
+    const size_t o_ft0 = take(sizeof(float) * d * Bp);
+    const size_t o_ft1 = take(sizeof(float) * d * Bp);
+    const size_t o_e = take(sizeof(float) * m * Bp);
+    const size_t o_pb = s->need_pbuf ? take(sizeof(float) * d * Bp) : 0;
+    const size_t o_lp = take(sizeof(LaneParams) * Bp);
     s->theta_cap = 1024;
-    const size_t o_th = take(sizeof(float) * (s->theta_cap + 2) * B);
+    const size_t o_th = take(sizeof(float) * (s->theta_cap + 2) * Bp);
     const size_t o_part = take(sizeof(double) * s->part_len);
-    const size_t o_red = take(sizeof(double) * 4 * B);
-    const size_t o_cl = take(sizeof(unsigned long long) * B);
-    const size_t o_tmc = take(sizeof(double) * B);
+    const size_t o_red = take(sizeof(double) * 4 * Bp);
+    const size_t o_cl = take(sizeof(unsigned long long) * Bp);
+    const size_t o_tmc = take(sizeof(double) * Bp);
     HIP_TRY(hipMalloc(&s->arena, off));
     char *base = static_cast<char *>(s->arena);
     s->g = reinterpret_cast<float *>(base + o_g);
@@ -673,11 +683,11 @@ static appga_status sess_alloc(appga_solve *s) {
 
 // Uploads theta_k for k in [k0, k0 + theta_cap] (lane-major within k).
 static appga_status sess_theta(appga_solve *s, int k0) {
-    const int B = s->B;
-    std::vector<float> th(static_cast<size_t>(s->theta_cap + 2) * B);
+    const int B = s->B, Bp = s->Bp;
+    std::vector<float> th(static_cast<size_t>(s->theta_cap + 2) * Bp, 0.0f);
     for (int kk = 0; kk < s->theta_cap + 2; ++kk)
         for (int b = 0; b < B; ++b)
-            th[static_cast<size_t>(kk) * B + b] = static_cast<float>(theta_of(s->prm[b], k0 + kk));
+            th[static_cast<size_t>(kk) * Bp + b] = static_cast<float>(theta_of(s->prm[b], k0 + kk));
     HIP_TRY(hipMemcpyAsync(s->theta, th.data(), th.size() * sizeof(float), hipMemcpyHostToDevice,
                            s->st));
     HIP_TRY(hipStreamSynchronize(s->st));
@@ -695,8 +705,12 @@ appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> 
     fa.col = mat->A.col;
     fa.val = mat->A.val;
     fa.row_scale = mat->A.row_scale;
+    fa.col32 = mat->A.col32;
+        fa.nnz_padded = mat->A.nnz_padded;
     fa.m = m;
+    fa.n_x = mat->A.n_cols;
     fa.B = B;
+    fa.Bp = s->Bp;
     fa.x = x;
     fa.g = s->g;
     fa.gamma = s->gamma;
@@ -759,12 +773,14 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
         if (he == hipSuccess && d_gamma)
             he = hipMemcpyAsync(s->gamma, d_gamma, sizeof(float) * m, hipMemcpyDeviceToDevice, s->st);
     } else {
-        he = launch_transpose(d_g, s->g, B, static_cast<int>(m), s->st);
+        he = launch_to_lanes(d_g, s->g, static_cast<int>(m), B, s->st);
         if (he == hipSuccess && d_gamma)
-            he = launch_transpose(d_gamma, s->gamma, B, static_cast<int>(m), s->st);
+            he = launch_to_lanes(d_gamma, s->gamma, static_cast<int>(m), B, s->st);
     }
-    std::vector<LaneParams> lp(B);
-    std::vector<float> gl(B);
+    // padding lanes get benign parameters (no regulariser, beta = 1, eps = 1)
+    const int Bp = s->Bp;
+    std::vector<LaneParams> lp(Bp, LaneParams{0.f, 0.f, 1.f, 1.f, 0.f, 0.f, 0.f, 0.f});
+    std::vector<float> gl(Bp, 0.0f);
     for (int b = 0; b < B; ++b) {
         const appga_params &p = params[b];
         lp[b] = LaneParams{static_cast<float>(p.lambda1), static_cast<float>(p.lambda2),
@@ -773,18 +789,19 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
         gl[b] = static_cast<float>(p.gamma_scalar);
     }
     if (he == hipSuccess)
-        he = hipMemcpyAsync(s->lp, lp.data(), sizeof(LaneParams) * B, hipMemcpyHostToDevice, s->st);
+        he = hipMemcpyAsync(s->lp, lp.data(), sizeof(LaneParams) * Bp, hipMemcpyHostToDevice, s->st);
     if (he == hipSuccess)
-        he = hipMemcpyAsync(s->gamma_lane, gl.data(), sizeof(float) * B, hipMemcpyHostToDevice, s->st);
-    if (he == hipSuccess) he = hipMemsetAsync(s->clamps, 0, sizeof(unsigned long long) * B, s->st);
+        he = hipMemcpyAsync(s->gamma_lane, gl.data(), sizeof(float) * Bp, hipMemcpyHostToDevice, s->st);
+    if (he == hipSuccess)
+        he = launch_fill(reinterpret_cast<float *>(s->clamps), 2 * static_cast<size_t>(Bp), 0.0f, s->st);
     // initial image f^0 = f^1
     if (he == hipSuccess) {
         if (d_f_init) {
             if (B == 1)
                 he = hipMemcpyAsync(s->f, d_f_init, sizeof(float) * d, hipMemcpyDeviceToDevice, s->st);
             else
-                he = launch_transpose(d_f_init, s->f, B, static_cast<int>(d), s->st);
-            if (he == hipSuccess) he = launch_copy(s->ft[0], s->f, static_cast<size_t>(d) * B, s->st);
+                he = launch_to_lanes(d_f_init, s->f, static_cast<int>(d), B, s->st);
+            if (he == hipSuccess) he = launch_copy(s->ft[0], s->f, static_cast<size_t>(d) * Bp, s->st);
         } else {
             // ACTc = sum g - sum gamma per solve (FP64), TMC = ACTc / (NPFOV * NPA)
             he = launch_sum_g_minus_gamma(static_cast<int>(m), B, s->g, s->gamma, s->gamma_lane,
@@ -801,7 +818,7 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
                 for (int r = 0; r < n; ++r)
                     for (int c = 0; c < n; ++c)
                         npfov += (c - ctr) * (c - ctr) + (r - ctr) * (r - ctr) <= rad2;
-                std::vector<double> tmc(B);
+                std::vector<double> tmc(Bp, 0.0);
                 for (int b = 0; b < B; ++b) {
                     if (!std::isfinite(actc[b])) {
                         fail(APPGA_E_NONFINITE, "non-finite sum of the data of solve %d", b);
@@ -813,7 +830,7 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
                     }
                     tmc[b] = actc[b] / (static_cast<double>(npfov) * mat->geom.n_angles);
                 }
-                he = hipMemcpyAsync(s->tmc, tmc.data(), sizeof(double) * B, hipMemcpyHostToDevice, s->st);
+                he = hipMemcpyAsync(s->tmc, tmc.data(), sizeof(double) * Bp, hipMemcpyHostToDevice, s->st);
                 if (he == hipSuccess) he = launch_disk_init(n, B, s->tmc, s->f, s->ft[0], s->st);
             }
         }
@@ -845,8 +862,12 @@ appga_status sess_step(appga_solve *s, int n_iters) {
         fa.col = mat->A.col;
         fa.val = mat->A.val;
         fa.row_scale = mat->A.row_scale;
+        fa.col32 = mat->A.col32;
+        fa.nnz_padded = mat->A.nnz_padded;
         fa.m = mat->A.n_rows;
+        fa.n_x = mat->A.n_cols;
         fa.B = B;
+        fa.Bp = s->Bp;
         fa.x = s->ft[s->cur];
         fa.g = s->g;
         fa.gamma = s->gamma;
@@ -854,6 +875,7 @@ appga_status sess_step(appga_solve *s, int n_iters) {
         fa.out = s->e;
         fa.mode = FM_RATIO;
         fa.scale_out = 1;
+        fa.fwd_wgs = mat->fwd_wgs;
         fa.clamps = s->clamps;
         HIP_TRY(timed_launch(s->ctx, B == 1 ? "forward_single" : "forward_batch", s->st,
                              [&] { return launch_forward(mat->A, fa, mat->group_fwd, s->st); }));
@@ -862,15 +884,19 @@ appga_status sess_step(appga_solve *s, int n_iters) {
         sa.col = mat->AT.col;
         sa.val = mat->AT.val;
         sa.row_scale = mat->AT.row_scale;
+        sa.col32 = mat->AT.col32;
+        sa.nnz_padded = mat->AT.nnz_padded;
         sa.n = mat->geom.n;
+        sa.m = mat->A.n_rows;
         sa.B = B;
+        sa.Bp = s->Bp;
         sa.e = s->e;
         sa.ft = s->ft[s->cur];
         sa.f = s->f;
         sa.ft_next = s->ft[s->cur ^ 1];
         sa.lam = mat->lam;
         sa.lp = s->lp;
-        sa.theta_next = s->theta + static_cast<size_t>(k + 1 - s->theta_base) * B;
+        sa.theta_next = s->theta + static_cast<size_t>(k + 1 - s->theta_base) * s->Bp;
         sa.pbuf = s->pbuf;
         if (p0.precond == APPGA_PRECOND_FIXED)
             sa.pmode = PM_FIXED;
@@ -913,7 +939,7 @@ appga_status sess_end(appga_solve *s, float *d_out, appga_stats *stats, bool fre
         if (B == 1)
             HIP_TRY(hipMemcpyAsync(d_out, s->f, sizeof(float) * d, hipMemcpyDeviceToDevice, s->st));
         else
-            HIP_TRY(launch_transpose(s->f, d_out, static_cast<int>(d), B, s->st));
+            HIP_TRY(launch_from_lanes(s->f, d_out, static_cast<int>(d), B, s->st));
     }
     HIP_TRY(hipStreamSynchronize(s->st));
     const double secs =
@@ -1082,7 +1108,7 @@ extern "C" appga_status appga_reconstruct_batch_device(appga_ctx *ctx, const app
 
 namespace {
 
-// Temporary [index][B] buffers for the operator entry points.
+// Temporary buffers of the operator entry points, in the layout of B.
 struct OpBufs {
     void *mem = nullptr;
     ~OpBufs() { hipFree(mem); }
@@ -1096,7 +1122,7 @@ appga_status to_internal(const float *src, float *dst, int B, int64_t len, hipSt
     if (B == 1)
         HIP_TRY(hipMemcpyAsync(dst, src, sizeof(float) * len, hipMemcpyDeviceToDevice, st));
     else
-        HIP_TRY(launch_transpose(src, dst, B, static_cast<int>(len), st));
+        HIP_TRY(launch_to_lanes(src, dst, static_cast<int>(len), B, st));
     return APPGA_OK;
 }
 
@@ -1104,7 +1130,7 @@ appga_status from_internal(const float *src, float *dst, int B, int64_t len, hip
     if (B == 1)
         HIP_TRY(hipMemcpyAsync(dst, src, sizeof(float) * len, hipMemcpyDeviceToDevice, st));
     else
-        HIP_TRY(launch_transpose(src, dst, static_cast<int>(len), B, st));
+        HIP_TRY(launch_from_lanes(src, dst, static_cast<int>(len), B, st));
     return APPGA_OK;
 }
 
@@ -1117,20 +1143,25 @@ appga_status op_forward_impl(appga_ctx *ctx, const appga_matrix *mat, int B, con
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = pick_stream(ctx, stream);
     const int64_t m = mat->A.n_rows, d = mat->A.n_cols;
+    const int Bp = pad_lanes(B);
     OpBufs ob;
-    const size_t nf = static_cast<size_t>(d) * B + 4 * static_cast<size_t>(m) * B;
+    const size_t nf = static_cast<size_t>(d) * Bp + 3 * static_cast<size_t>(m) * Bp;
     HIP_TRY(hipMalloc(&ob.mem, sizeof(float) * nf));
-    float *x = static_cast<float *>(ob.mem), *g = x + d * B, *gam = g + m * B, *y = gam + m * B;
+    float *x = static_cast<float *>(ob.mem), *g = x + d * Bp, *gam = g + m * Bp, *y = gam + m * Bp;
     ST_TRY(to_internal(d_x, x, B, d, st));
     if (d_g) ST_TRY(to_internal(d_g, g, B, m, st));
     if (d_gamma) ST_TRY(to_internal(d_gamma, gam, B, m, st));
     FwdArgs fa{};
     fa.row_ptr = mat->A.row_ptr;
     fa.col = mat->A.col;
+    fa.col32 = mat->A.col32;
+        fa.nnz_padded = mat->A.nnz_padded;
     fa.val = mat->A.val;
     fa.row_scale = mat->A.row_scale;
     fa.m = static_cast<int>(m);
+    fa.n_x = static_cast<int>(d);
     fa.B = B;
+    fa.Bp = Bp;
     fa.x = x;
     fa.g = g;
     fa.gamma = d_gamma ? gam : nullptr;
@@ -1138,6 +1169,7 @@ appga_status op_forward_impl(appga_ctx *ctx, const appga_matrix *mat, int B, con
     fa.out = y;
     fa.mode = mode;
     fa.scale_out = scale_out;
+    fa.fwd_wgs = mat->fwd_wgs;
     HIP_TRY(timed_launch(ctx, B == 1 ? "op_forward_single" : "op_forward_batch", st,
                          [&] { return launch_forward(mat->A, fa, mat->group_fwd, st); }));
     ST_TRY(from_internal(y, d_y, B, m, st));
@@ -1154,44 +1186,48 @@ appga_status op_step_impl(appga_ctx *ctx, const appga_matrix *mat, int n, int B,
     hipStream_t st = pick_stream(ctx, stream);
     const int64_t d = static_cast<int64_t>(n) * n;
     const int64_t m = mat ? mat->A.n_rows : 0;
+    const int Bp = pad_lanes(B);
     OpBufs ob;
-    const size_t bytes = sizeof(float) * (static_cast<size_t>(d) * B * 4 + static_cast<size_t>(m) * B + B) +
-                         sizeof(LaneParams) * B + 256;
-    HIP_TRY(hipMalloc(&ob.mem, bytes));
+    const size_t nfl = static_cast<size_t>(d) * Bp * 4 + static_cast<size_t>(m) * Bp + Bp;
+    const size_t lp_off = (sizeof(float) * nfl + 255) / 256 * 256;
+    HIP_TRY(hipMalloc(&ob.mem, lp_off + sizeof(LaneParams) * Bp));
     float *e = static_cast<float *>(ob.mem);
-    float *ft = e + m * B, *f = ft + d * B, *ftn = f + d * B, *out = ftn + d * B, *th = out + d * B;
-    LaneParams *lp = reinterpret_cast<LaneParams *>(reinterpret_cast<char *>(th + B) + 256 -
-                                                    (reinterpret_cast<uintptr_t>(th + B) & 255));
+    float *ft = e + m * Bp, *f = ft + d * Bp, *ftn = f + d * Bp, *out = ftn + d * Bp, *th = out + d * Bp;
+    LaneParams *lp = reinterpret_cast<LaneParams *>(static_cast<char *>(ob.mem) + lp_off);
     if (d_e) ST_TRY(to_internal(d_e, e, B, m, st));
     if (d_e && scale_rows && mat && mat->A.row_scale)
         HIP_TRY(launch_scale_rows(e, mat->A.row_scale, static_cast<int>(m), B, st));
     if (d_ft)
         ST_TRY(to_internal(d_ft, ft, B, d, st));
     else
-        HIP_TRY(launch_fill(ft, static_cast<size_t>(d) * B, 0.0f, st));
+        HIP_TRY(launch_fill(ft, static_cast<size_t>(d) * Bp, 0.0f, st));
     if (d_f)
         ST_TRY(to_internal(d_f, f, B, d, st));
     else
-        HIP_TRY(launch_fill(f, static_cast<size_t>(d) * B, 0.0f, st));
-    std::vector<LaneParams> hlp(B);
-    std::vector<float> hth(B, 0.0f);
+        HIP_TRY(launch_fill(f, static_cast<size_t>(d) * Bp, 0.0f, st));
+    std::vector<LaneParams> hlp(Bp, LaneParams{0.f, 0.f, 1.f, 1.f, 0.f, 0.f, 0.f, 0.f});
+    std::vector<float> hth(Bp, 0.0f);
     for (int b = 0; b < B; ++b) {
         hlp[b] = LaneParams{static_cast<float>(lambda1[b]), static_cast<float>(lambda2[b]),
                             static_cast<float>(eps[b]), beta ? static_cast<float>(beta[b]) : 1.0f,
                             0.f, 0.f, 0.f, 0.f};
         if (theta_next) hth[b] = static_cast<float>(theta_next[b]);
     }
-    HIP_TRY(hipMemcpyAsync(lp, hlp.data(), sizeof(LaneParams) * B, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(th, hth.data(), sizeof(float) * B, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(lp, hlp.data(), sizeof(LaneParams) * Bp, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(th, hth.data(), sizeof(float) * Bp, hipMemcpyHostToDevice, st));
     StepArgs sa{};
     DevCsr dummy;
     const DevCsr &AT = mat ? mat->AT : dummy;
     sa.row_ptr = AT.row_ptr;
     sa.col = AT.col;
+    sa.col32 = AT.col32;
+    sa.nnz_padded = AT.nnz_padded;
     sa.val = AT.val;
     sa.row_scale = AT.row_scale;
     sa.n = n;
+    sa.m = static_cast<int>(m);
     sa.B = B;
+    sa.Bp = Bp;
     sa.e = e;
     sa.ft = ft;
     sa.f = f;

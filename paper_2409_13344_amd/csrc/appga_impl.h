@@ -38,6 +38,7 @@ struct appga_matrix {
     std::vector<int32_t> user_col;
     int group_fwd = 16, group_back = 16;
     int xcd_remap = 0;
+    int fwd_wgs = 2048;                // batched forward: workgroups of the row-strided grid
     mutable std::atomic<int> inflight{0};
 };
 
@@ -45,6 +46,7 @@ struct appga_solve {
     appga_ctx *ctx = nullptr;
     const appga_matrix *mat = nullptr;
     int B = 0;
+    int Bp = 1;  // padded lane count (1 for B = 1, else a multiple of 64)
     hipStream_t st = nullptr;
     std::vector<appga_params> prm;
     bool has_gamma = false, need_pbuf = false;

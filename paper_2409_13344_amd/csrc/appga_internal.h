@@ -12,9 +12,11 @@ namespace appga {
 // Storage types of matrix values (same numbering as appga_dtype).
 enum ValType : int { VT_F32 = 1, VT_BF16 = 2, VT_F16 = 3, VT_FP8 = 4 };
 
-// Entries per chunk: every stored row is padded with zero entries to a
-// multiple of this, so kernels read whole 8-entry chunks without tails.
+// Entries per chunk read by one lane of the B = 1 kernels (16-byte loads).
 constexpr int kChunk = 8;
+// Every stored row is padded with zero entries to a multiple of this (two
+// chunks: the B > 1 kernels stream rows in groups of 16 entries).
+constexpr int kRowPad = 16;
 
 // One stored sparse operator (A, or the transpose used for A^T), CSR with
 // rows padded to kChunk entries.  Device pointers.
@@ -22,8 +24,9 @@ struct DevCsr {
     int32_t n_rows = 0, n_cols = 0;
     int64_t nnz = 0;          // real entries
     int64_t nnz_padded = 0;   // stored entries
-    int32_t *row_ptr = nullptr;  // n_rows + 1, multiples of kChunk
-    void *col = nullptr;         // uint16_t when idx16, else uint32_t
+    int32_t *row_ptr = nullptr;  // n_rows + 1, multiples of kRowPad
+    void *col = nullptr;         // uint16_t when idx16, else uint32_t (B = 1 kernels)
+    uint32_t *col32 = nullptr;   // byte offset col * 256 of each entry's 64-lane record (B > 1 kernels)
     void *val = nullptr;         // float / bf16 / f16 / fp8 (uint8)
     float *row_scale = nullptr;  // FP8 only: value = scale[row] * decode(q)
     int idx16 = 1;
@@ -62,10 +65,14 @@ enum FwdMode : int {
 struct FwdArgs {
     const int32_t *row_ptr;
     const void *col;
+    const uint32_t *col32;
+    int64_t nnz_padded;
     const void *val;
     const float *row_scale;
     int m;                  // rows
-    int B;                  // solves; row stride of x / g / gamma / out
+    int n_x;                // columns (length of x per solve)
+    int B;                  // solves
+    int Bp;                 // padded lanes: 1 for B = 1, else a multiple of 64
     const float *x;         // [d][B]
     const float *g;         // [m][B]
     const float *gamma;     // [m][B] or null (then gamma_lane)
@@ -73,16 +80,21 @@ struct FwdArgs {
     float *out;             // [m][B]
     int mode;               // FwdMode
     int scale_out;          // FM_RATIO with FP8: write row_scale[i] * e_i (the transpose has no scales)
+    int fwd_wgs;            // B > 1: workgroups of the row-strided grid (0 = default)
     unsigned long long *clamps;  // floored-bin counter (may be null)
 };
 
 struct StepArgs {
     const int32_t *row_ptr;  // transpose (rows = pixels)
     const void *col;
+    const uint32_t *col32;
+    int64_t nnz_padded;
     const void *val;
     const float *row_scale;  // unused: FP8 transposes carry A's row scales in e
     int n;                   // image side N
-    int B;                   // solves; row stride
+    int m;                   // detector bins (length of e per solve)
+    int B;                   // solves
+    int Bp;                  // padded lanes: 1 for B = 1, else a multiple of 64
     const float *e;          // [m][B] ratio residual 1 - g / y
     const float *ft;         // [d][B] extrapolated point f~^k
     float *f;                // [d][B] f^k in, f^{k+1} out
@@ -111,7 +123,9 @@ hipError_t launch_reg_value(int n, int B, const float *x, const LaneParams *lp, 
 int reg_value_blocks(int n);
 hipError_t launch_reduce_partials(const double *part, int nblocks, int B, int ncomp, double *out,
                                   hipStream_t st);
-hipError_t launch_transpose(const float *in, float *out, int rows, int cols, hipStream_t st);
+int pad_lanes(int B);
+hipError_t launch_to_lanes(const float *in, float *out, int n, int B, hipStream_t st);
+hipError_t launch_from_lanes(const float *in, float *out, int n, int B, hipStream_t st);
 hipError_t launch_disk_init(int n, int B, const double *tmc, float *f, float *ft, hipStream_t st);
 hipError_t launch_sum_g_minus_gamma(int m, int B, const float *g, const float *gamma,
                                     const float *gamma_lane, double *part, hipStream_t st);

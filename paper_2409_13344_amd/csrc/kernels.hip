@@ -5,24 +5,26 @@
 //
 //  forward  : y = A f~ + gamma and e = 1 - g / max(y, tau)      (grad F, first half)
 //  step     : grad F = A^T e over the stored transpose, the SHOITV gradient
-//             B1^T w1 B1 f~ + B2^T w2 B2 f~ from an LDS halo tile, the EM
+//             B1^T w1 B1 f~ + B2^T w2 B2 f~ from LDS tiles, the EM
 //             preconditioner P = beta f^k / Lambda, f^{k+1} = max(f~ - P (grad F +
 //             grad R), 0) and the next extrapolation f~^{k+1} = f^{k+1} +
 //             theta_{k+1} (f^{k+1} - f^k) (eq. GNtheta)
 //
-// Layouts: every per-solve vector is stored [index][B] (solves innermost).
-//  - B = 1 ("single") kernels give each matrix row a group of G lanes; each
-//    lane reads whole 8-entry chunks (16-byte index and value loads) and the
-//    group reduces with cross-lane shuffles.
-//  - B > 1 ("batch") kernels give each row one wave whose 64 lanes are 64
-//    solves: the matrix entry is wave-uniform (scalar loads) and the gather of
-//    x[col][0:B] is one coalesced B*4-byte access per nonzero.
-// Matrix rows are padded with zero entries to multiples of 8 (kChunk), so no
+// Layouts of per-solve vectors:
+//  - B = 1: plain vectors.  The "single" kernels give each matrix row a group
+//    of G lanes; each lane reads whole 8-entry chunks (16-byte index and value
+//    loads) and the group reduces with cross-lane shuffles.
+//  - B > 1: the lane layout.  Solves are grouped in chunks of 64 (one
+//    wavefront); element i of solve b lives at ((b / 64) n + i) 64 + b % 64.
+//    The "batch" kernels give each row one wave whose lanes are the 64 solves
+//    of a chunk (blockIdx.y): a matrix entry is wave-uniform (scalar loads of a
+//    precomputed byte offset col * 256 and of the value), and the gather of
+//    x[col][0:64] is one buffer load with that offset in an SGPR, so a nonzero
+//    costs one gather and one FMA.
+// Matrix rows are padded with zero entries to multiples of 16 (kRowPad), so no
 // kernel handles a ragged tail inside a row.
 
 #include <hip/hip_runtime.h>
-#include <hip/hip_bf16.h>
-#include <hip/hip_fp16.h>
 
 #include <algorithm>
 #include <type_traits>
@@ -99,101 +101,196 @@ __device__ __forceinline__ void load_vals8(const void *__restrict__ val, int64_t
 // Floor of y = A x + gamma before the ratio: tau = 1e-6 gamma, or 1e-30 when gamma = 0.
 __device__ __forceinline__ float y_floor(float gam) { return gam > 0.0f ? 1e-6f * gam : 1e-30f; }
 
+// Buffer resource over `bytes` bytes at p (gfx9-family descriptor word 3).
+// Loads through it are range-checked by the hardware (out of range reads 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), static_cast<short>(0),
+                                             static_cast<int>(bytes), 0x00020000);
+}
+
+template <int VT>
+__host__ __device__ constexpr uint32_t vbytes() {
+    return VT == VT_F32 ? 4u : (VT == VT_FP8 ? 1u : 2u);
+}
+
+// 4-byte load at byte offset voff (per lane) + soff (wave-uniform, in an SGPR).
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// Index of element i of solve b in the lane layout of vectors of length n.
+__device__ __forceinline__ size_t lidx(int i, int b, int n) {
+    return (static_cast<size_t>(b >> 6) * n + i) * 64 + (b & 63);
+}
+
 // ------------------------------------------------------------------------
-// Forward projection, B = 1: G lanes per row.
+// Row dot products
 // ------------------------------------------------------------------------
 
+// Raw value bits of stored entry k + lane (one coalesced vector load per 64 entries).
+template <int VT>
+__device__ __forceinline__ uint32_t load_val_lane(__amdgpu_buffer_rsrc_t vr, int k) {
+    const uint32_t lane = __lane_id();
+    if constexpr (VT == VT_F32)
+        return __builtin_amdgcn_raw_buffer_load_b32(vr, 4u * (static_cast<uint32_t>(k) + lane), 0, 0);
+    else if constexpr (VT == VT_FP8)
+        return __builtin_amdgcn_raw_buffer_load_b8(vr, static_cast<uint32_t>(k) + lane, 0, 0);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b16(vr, 2u * (static_cast<uint32_t>(k) + lane), 0, 0);
+}
+
+template <int VT>
+__device__ __forceinline__ float decode_val(uint32_t raw) {
+    if constexpr (VT == VT_F32) return __uint_as_float(raw);
+    else if constexpr (VT == VT_BF16) return bf16_to_f32(raw & 0xFFFFu);
+    else if constexpr (VT == VT_F16) return f16_to_f32(raw & 0xFFFFu);
+    else return fp8_to_f32(raw & 0xFFu);
+}
+
+// Lane-layout gather: sum_k val[k] * x[col[k]][lane] over the stored entries
+// [k0, k1) of one wave-uniform row, entries in order.  The matrix holds the
+// byte offset col * 256 of each entry's 64-lane record of x.  Each group of 64
+// entries is read with one coalesced vector load per array (lane l holds entry
+// k + l); v_readlane moves entry t into scalar registers, so a gather is one
+// buffer load with a scalar offset and the product one FMA with a scalar
+// operand.  The next group's loads are issued before the current gathers.
+// Rows are padded to multiples of 16 entries; loads past the array end read 0.
+template <int VT>
+__device__ __forceinline__ float gather_dot_lanes64(__amdgpu_buffer_rsrc_t cr,
+                                                    __amdgpu_buffer_rsrc_t vr,
+                                                    __amdgpu_buffer_rsrc_t xr, int k0, int k1,
+                                                    uint32_t voff) {
+    float acc = 0.0f;
+    const uint32_t lane = __lane_id();
+    int k = k0;
+    uint32_t vc = 0, vv = 0;
+    if (k < k1) {
+        vc = __builtin_amdgcn_raw_buffer_load_b32(cr, 4u * (static_cast<uint32_t>(k) + lane), 0, 0);
+        vv = load_val_lane<VT>(vr, k);
+    }
+    while (k < k1) {
+        const int n = k1 - k;   // multiple of 16
+        const int kn = k + 64;
+        uint32_t vc2 = 0, vv2 = 0;
+        if (kn < k1) {
+            vc2 = __builtin_amdgcn_raw_buffer_load_b32(cr, 4u * (static_cast<uint32_t>(kn) + lane), 0, 0);
+            vv2 = load_val_lane<VT>(vr, kn);
+        }
+#pragma unroll
+        for (int t0 = 0; t0 < 64; t0 += 16) {
+            if (t0 < n) {
+                float x[16];
+                uint32_t sv[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const uint32_t sc = __builtin_amdgcn_readlane(vc, t0 + t);
+                    sv[t] = __builtin_amdgcn_readlane(vv, t0 + t);
+                    x[t] = buf_load(xr, voff, sc);
+                }
+#pragma unroll
+                for (int t = 0; t < 16; ++t) acc = fmaf(decode_val<VT>(sv[t]), x[t], acc);
+            }
+        }
+        vc = vc2;
+        vv = vv2;
+        k = kn;
+    }
+    return acc;
+}
+
+// B = 1: partial dot product of lane gl of a G-lane group over the stored
+// entries [k0, k1): lane gl takes chunks gl, gl + G, ...; the gather offset is
+// per lane.
+template <typename IT, int VT, int G>
+__device__ __forceinline__ float gather_dot_group(const IT *__restrict__ col,
+                                                  const void *__restrict__ val,
+                                                  __amdgpu_buffer_rsrc_t xr, int k0, int k1,
+                                                  int gl) {
+    float acc = 0.0f;
+    for (int k = k0 + gl * kChunk; k < k1; k += G * kChunk) {
+        uint32_t c[8];
+        float v[8], xv[8];
+        load_cols8<IT>(col, k, c);
+        load_vals8<VT>(val, k, v);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) xv[t] = buf_load(xr, 4u * c[t], 0u);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc = fmaf(v[t], xv[t], acc);
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------------------
+// Forward projection + Poisson ratio
+// ------------------------------------------------------------------------
+
+// Epilogue for row `row`, solve b, at vector index o; y = acc + gamma.
+template <int VT>
+__device__ __forceinline__ void fwd_epilogue(const FwdArgs &a, int row, int b, size_t o, float acc,
+                                             float gam, bool count) {
+    if constexpr (VT == VT_FP8) acc *= a.row_scale[row];
+    float y = acc + gam;
+    if (a.mode == FM_PROJ) {
+        a.out[o] = y;
+        return;
+    }
+    const float tau = y_floor(gam);
+    if (y < tau) {
+        y = tau;
+        if (count && a.clamps) atomicAdd(a.clamps + b, 1ull);
+    }
+    float ev = 1.0f - a.g[o] / y;
+    if constexpr (VT == VT_FP8) {
+        if (a.scale_out) ev *= a.row_scale[row];
+    }
+    a.out[o] = ev;
+}
+
+// B = 1: G lanes per row, 256 / G rows per workgroup.
 template <typename IT, int VT, int G>
 __global__ __launch_bounds__(256) void k_fwd_single(FwdArgs a) {
     const int lane = threadIdx.x & 63;
     const int gl = lane & (G - 1);
     const int row = blockIdx.x * (256 / G) + threadIdx.x / G;
     const IT *__restrict__ col = static_cast<const IT *>(a.col);
-    const float *__restrict__ x = a.x;
+    const auto xr = make_rsrc(a.x, 4u * static_cast<uint32_t>(a.n_x));
     float acc = 0.0f;
-    if (row < a.m) {
-        const int k0 = a.row_ptr[row], k1 = a.row_ptr[row + 1];
-        for (int k = k0 + gl * kChunk; k < k1; k += G * kChunk) {
-            uint32_t c[8];
-            float v[8], xv[8];
-            load_cols8<IT>(col, k, c);
-            load_vals8<VT>(a.val, k, v);
-#pragma unroll
-            for (int t = 0; t < 8; ++t) xv[t] = x[c[t]];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) acc = fmaf(v[t], xv[t], acc);
-        }
-    }
+    if (row < a.m)
+        acc = gather_dot_group<IT, VT, G>(col, a.val, xr, a.row_ptr[row], a.row_ptr[row + 1], gl);
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (row < a.m && gl == 0) {
-        if constexpr (VT == VT_FP8) acc *= a.row_scale[row];
         const float gam = a.gamma ? a.gamma[row] : (a.gamma_lane ? a.gamma_lane[0] : 0.0f);
-        float y = acc + gam;
-        if (a.mode == FM_PROJ) {
-            a.out[row] = y;
-        } else {
-            const float tau = y_floor(gam);
-            if (y < tau) {
-                y = tau;
-                if (a.clamps) atomicAdd(a.clamps, 1ull);
-            }
-            float ev = 1.0f - a.g[row] / y;
-            if constexpr (VT == VT_FP8) if (a.scale_out) ev *= a.row_scale[row];
-            a.out[row] = ev;
-        }
+        fwd_epilogue<VT>(a, row, 0, row, acc, gam, true);
     }
 }
 
-// ------------------------------------------------------------------------
-// Forward projection, B > 1: one wave per row, lanes = solves (64 per
-// blockIdx.y chunk).
-// ------------------------------------------------------------------------
-
-template <typename IT, int VT>
+// B > 1: one wave per row at a time, lanes = the 64 solves of chunk
+// blockIdx.y; waves stride over the rows (the grid holds about one wave per
+// wave slot of the device, so per-wave set-up is paid once, not per row).
+template <int VT>
 __global__ __launch_bounds__(256) void k_fwd_batch(FwdArgs a) {
     const int lane = threadIdx.x & 63;
-    const int row = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    if (row >= a.m) return;
-    const int B = a.B;
-    const int b = blockIdx.y * 64 + lane;
-    const bool act = b < B;
-    const int bl = act ? b : B - 1;  // idle lanes re-read a valid element (same cache line)
-    const IT *__restrict__ col = static_cast<const IT *>(a.col);
-    const float *__restrict__ x = a.x;
-    const int k0 = a.row_ptr[row], k1 = a.row_ptr[row + 1];
-    float acc = 0.0f;
-    for (int k = k0; k < k1; k += kChunk) {
-        uint32_t c[8];
-        float v[8], xv[8];
-        load_cols8<IT>(col, k, c);
-        load_vals8<VT>(a.val, k, v);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) xv[t] = x[static_cast<size_t>(c[t]) * B + bl];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) acc = fmaf(v[t], xv[t], acc);
-    }
-    if (!act) return;
-    if constexpr (VT == VT_FP8) acc *= a.row_scale[row];
-    const size_t o = static_cast<size_t>(row) * B + b;
-    const float gam = a.gamma ? a.gamma[o] : (a.gamma_lane ? a.gamma_lane[b] : 0.0f);
-    float y = acc + gam;
-    if (a.mode == FM_PROJ) {
-        a.out[o] = y;
-    } else {
-        const float tau = y_floor(gam);
-        if (y < tau) {
-            y = tau;
-            if (a.clamps) atomicAdd(a.clamps + b, 1ull);
-        }
-        float ev = 1.0f - a.g[o] / y;
-        if constexpr (VT == VT_FP8) if (a.scale_out) ev *= a.row_scale[row];
-        a.out[o] = ev;
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int nwaves = gridDim.x * 4;
+    const int chunk = blockIdx.y;
+    const int b = chunk * 64 + lane;
+    const auto xr = make_rsrc(reinterpret_cast<const char *>(a.x) + static_cast<size_t>(chunk) * a.n_x * 256,
+                              256u * static_cast<uint32_t>(a.n_x));
+    const float gl = a.gamma_lane ? a.gamma_lane[b] : 0.0f;
+    const auto cr = make_rsrc(a.col32, 4u * static_cast<uint32_t>(a.nnz_padded));
+    const auto vr = make_rsrc(a.val, static_cast<uint32_t>(a.nnz_padded) * vbytes<VT>());
+    for (int row = wave; row < a.m; row += nwaves) {
+        const int k0 = a.row_ptr[row], k1 = a.row_ptr[row + 1];
+        const float acc = gather_dot_lanes64<VT>(cr, vr, xr, k0, k1, 4u * lane);
+        const size_t o = (static_cast<size_t>(chunk) * a.m + row) * 64 + lane;
+        const float gam = a.gamma ? a.gamma[o] : gl;
+        fwd_epilogue<VT>(a, row, b, o, acc, gam, b < a.B);
     }
 }
 
 // ------------------------------------------------------------------------
-// SHOITV gradient on a tile (Section 2.1 operators, Section 2.2 gradient).
+// SHOITV gradient (Section 2.1 operators, Section 2.2 gradient).
 //
 // With image index j = r*N + c, X (x) Y acts as X along r and Y along c, and
 // (Dx)_c = [c>=1](x_c - x_{c-1}), (D^T y)_c = [c>=1] y_c - [c<=N-2] y_{c+1},
@@ -203,8 +300,10 @@ __global__ __launch_bounds__(256) void k_fwd_batch(FwdArgs a) {
 // weights w1 = lambda1 / max(|u|, eps), w2 = lambda2 / max(|v|, eps), and
 //   grad R = (I(x)D^T)(w1 u1) + (D^T(x)I)(w1 u2) + (I(x)L)(w2 v1)
 //          + (-D(x)D^T)(w2 v2) + (L(x)I)(w2 v3) + (D^T(x)-D)(w2 v4).
-// The value at (r, c) needs the weighted vectors at (r, c) and six
-// neighbours, which need f within a radius of 2.
+// grad R at (r, c) needs the weighted vectors at (r, c) and six neighbours
+// within one pixel, which need f within a radius of 2.  A 4 x 4 tile needs
+// the weighted vectors on the 6 x 6 block around it (computed once each, kept
+// in LDS) and f on the 8 x 8 block around it.
 // ------------------------------------------------------------------------
 
 // The six components at (r, c) (0 <= r, c < N); F(r, c) reads the image.
@@ -244,41 +343,34 @@ __device__ __forceinline__ void pq6(const Fn &F, int r, int c, int N, float l1, 
     o[2] *= w2; o[3] *= w2; o[4] *= w2; o[5] *= w2;
 }
 
-template <typename Fn>
-__device__ __forceinline__ float grad_reg_at(const Fn &F, int r, int c, int N, float l1, float l2,
-                                             float eps) {
+// grad R at (r, c) from the weighted vectors; Q(dr, dc, k) reads component k
+// at (r + dr, c + dc) (only in-image positions are read).
+template <typename Qf>
+__device__ __forceinline__ float combine_grad(const Qf &Q, int r, int c, int N) {
     const bool cl = c >= 1, cr = c <= N - 2, ru = r >= 1, rd = r <= N - 2;
-    float P0[6], Pr[6] = {0}, Pd[6] = {0}, Pl[6] = {0}, Pu[6] = {0}, Pur[6] = {0}, Pdl[6] = {0};
-    pq6(F, r, c, N, l1, l2, eps, P0);
-    if (cr) pq6(F, r, c + 1, N, l1, l2, eps, Pr);
-    if (rd) pq6(F, r + 1, c, N, l1, l2, eps, Pd);
-    if (cl) pq6(F, r, c - 1, N, l1, l2, eps, Pl);
-    if (ru) pq6(F, r - 1, c, N, l1, l2, eps, Pu);
-    if (ru && cr) pq6(F, r - 1, c + 1, N, l1, l2, eps, Pur);
-    if (rd && cl) pq6(F, r + 1, c - 1, N, l1, l2, eps, Pdl);
     // (I (x) D^T) p1 and (D^T (x) I) p2
-    float g = (cl ? P0[0] : 0.0f) - (cr ? Pr[0] : 0.0f);
-    g += (ru ? P0[1] : 0.0f) - (rd ? Pd[1] : 0.0f);
+    float g = (cl ? Q(0, 0, 0) : 0.0f) - (cr ? Q(0, 1, 0) : 0.0f);
+    g += (ru ? Q(0, 0, 1) : 0.0f) - (rd ? Q(1, 0, 1) : 0.0f);
     // (I (x) L) q1
-    g += (cr ? Pr[2] - P0[2] : 0.0f) + (cl ? Pl[2] - P0[2] : 0.0f);
+    g += (cr ? Q(0, 1, 2) - Q(0, 0, 2) : 0.0f) + (cl ? Q(0, -1, 2) - Q(0, 0, 2) : 0.0f);
     // (-D (x) D^T) q2: t(r') = [c>=1] q2(r', c) - [c<=N-2] q2(r', c+1); -[r>=1](t(r) - t(r-1))
     if (ru) {
-        const float t0 = (cl ? P0[3] : 0.0f) - (cr ? Pr[3] : 0.0f);
-        const float t1 = (cl ? Pu[3] : 0.0f) - (cr ? Pur[3] : 0.0f);
+        const float t0 = (cl ? Q(0, 0, 3) : 0.0f) - (cr ? Q(0, 1, 3) : 0.0f);
+        const float t1 = (cl ? Q(-1, 0, 3) : 0.0f) - (cr ? Q(-1, 1, 3) : 0.0f);
         g -= t0 - t1;
     }
     // (L (x) I) q3
-    g += (rd ? Pd[4] - P0[4] : 0.0f) + (ru ? Pu[4] - P0[4] : 0.0f);
+    g += (rd ? Q(1, 0, 4) - Q(0, 0, 4) : 0.0f) + (ru ? Q(-1, 0, 4) - Q(0, 0, 4) : 0.0f);
     // (D^T (x) -D) q4: s(r') = -[c>=1](q4(r', c) - q4(r', c-1)); [r>=1] s(r) - [r<=N-2] s(r+1)
     if (cl) {
-        const float s0 = -(P0[5] - Pl[5]);
-        const float s1 = -(Pd[5] - Pdl[5]);
-        g += (ru ? s0 : 0.0f) - (rd ? s1 : 0.0f);
+        const float s0 = -(Q(0, 0, 5) - Q(0, -1, 5));
+        const float s1 = rd ? -(Q(1, 0, 5) - Q(1, -1, 5)) : 0.0f;
+        g += (ru ? s0 : 0.0f) - s1;
     }
     return g;
 }
 
-// Preconditioned gradient step, prox and extrapolation for one pixel/solve.
+// Preconditioner value for one pixel/solve (stores it in frozen-update mode).
 __device__ __forceinline__ float precond(int pmode, float fk, float lam, const LaneParams &lp,
                                          float *pbuf, size_t o) {
     float P;
@@ -307,53 +399,51 @@ __device__ __forceinline__ int tile_of(int wg, int tiles_x, int tiles_y, int rem
 }
 
 // ------------------------------------------------------------------------
-// Step kernel, B = 1.  Tile of 4 x 4 pixels per workgroup (256 threads);
-// groups of G lanes back-project one pixel each, then 16 threads apply the
-// stencil and the update from an 8 x 8 halo in LDS.
+// Step kernel, B = 1.  Tile of 4 x 4 pixels per workgroup of 16 G threads:
+// lane group p (G lanes) back-projects pixel p; 36 threads compute the
+// weighted vectors on the 6 x 6 block from the 8 x 8 halo of f~ in LDS;
+// 16 threads combine them and apply the update.
 // ------------------------------------------------------------------------
 
 template <typename IT, int VT, int G>
-__global__ __launch_bounds__(256) void k_step_single(StepArgs a) {
+__global__ __launch_bounds__(16 * G) void k_step_single(StepArgs a) {
     __shared__ float halo[64];
+    __shared__ float pqs[6][36];
     __shared__ float gfs[16];
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int gl = lane & (G - 1);
-    const int grp = tid / G;
-    constexpr int NG = 256 / G;
+    const int gl = tid & (G - 1);
+    const int p = tid / G;
     const int N = a.n;
     const int tiles_x = a.tiles_x, tiles_y = (N + 3) / 4;
     const int tile = tile_of(blockIdx.x, tiles_x, tiles_y, a.xcd_remap);
     const int r0 = (tile / tiles_x) * 4, c0 = (tile % tiles_x) * 4;
     const IT *__restrict__ col = static_cast<const IT *>(a.col);
-    const float *__restrict__ e = a.e;
 
     if (a.out_mode != SO_REG) {
-        for (int p = grp; p < 16; p += NG) {
-            const int r = r0 + (p >> 2), c = c0 + (p & 3);
-            float acc = 0.0f;
-            if (r < N && c < N) {
-                const int j = r * N + c;
-                const int k0 = a.row_ptr[j], k1 = a.row_ptr[j + 1];
-                for (int k = k0 + gl * kChunk; k < k1; k += G * kChunk) {
-                    uint32_t cc[8];
-                    float v[8], ev[8];
-                    load_cols8<IT>(col, k, cc);
-                    load_vals8<VT>(a.val, k, v);
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) ev[t] = e[cc[t]];
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) acc = fmaf(v[t], ev[t], acc);
-                }
-            }
-#pragma unroll
-            for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if (gl == 0) gfs[p] = acc;
+        const int rp = r0 + (p >> 2), cp = c0 + (p & 3);
+        float acc = 0.0f;
+        if (rp < N && cp < N) {
+            const int j = rp * N + cp;
+            const auto er = make_rsrc(a.e, 4u * static_cast<uint32_t>(a.m));
+            acc = gather_dot_group<IT, VT, G>(col, a.val, er, a.row_ptr[j], a.row_ptr[j + 1], gl);
         }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (gl == 0) gfs[p] = acc;
     }
     if (tid < 64) {
         const int hr = r0 - 2 + (tid >> 3), hc = c0 - 2 + (tid & 7);
         halo[tid] = (hr >= 0 && hr < N && hc >= 0 && hc < N) ? a.ft[hr * N + hc] : 0.0f;
+    }
+    __syncthreads();
+    const LaneParams lp = a.lp[0];
+    auto F = [&](int rr, int cc) { return halo[(rr - r0 + 2) * 8 + (cc - c0 + 2)]; };
+    if (tid < 36) {
+        const int rr = r0 - 1 + tid / 6, cc = c0 - 1 + tid % 6;
+        float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (rr >= 0 && rr < N && cc >= 0 && cc < N) pq6(F, rr, cc, N, lp.lambda1, lp.lambda2, lp.eps, o);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) pqs[k][tid] = o[k];
     }
     __syncthreads();
     if (tid >= 16) return;
@@ -361,25 +451,26 @@ __global__ __launch_bounds__(256) void k_step_single(StepArgs a) {
     const bool in = r < N && c < N;
     double dd = 0.0, nn = 0.0;
     if (in) {
-        const LaneParams lp = a.lp[0];
-        auto F = [&](int rr, int cc) { return halo[(rr - r0 + 2) * 8 + (cc - c0 + 2)]; };
-        const float gR = grad_reg_at(F, r, c, N, lp.lambda1, lp.lambda2, lp.eps);
         const int j = r * N + c;
+        auto Q = [&](int dr, int dc, int k) { return pqs[k][(r - r0 + 1 + dr) * 6 + (c - c0 + 1 + dc)]; };
         if (a.out_mode == SO_BACK) {
             a.out[j] = gfs[tid];
-        } else if (a.out_mode == SO_REG) {
-            a.out[j] = gR;
         } else {
-            const float ftc = F(r, c);
-            const float fk = a.f[j];
-            const float P = precond(a.pmode, fk, a.lam[j], lp, a.pbuf, j);
-            const float z = ftc - P * (gfs[tid] + gR);
-            const float fn = z > 0.0f ? z : 0.0f;
-            a.f[j] = fn;
-            a.ft_next[j] = fn + a.theta_next[0] * (fn - fk);
-            const double df = static_cast<double>(fn) - static_cast<double>(fk);
-            dd = df * df;
-            nn = static_cast<double>(fn) * static_cast<double>(fn);
+            const float gR = combine_grad(Q, r, c, N);
+            if (a.out_mode == SO_REG) {
+                a.out[j] = gR;
+            } else {
+                const float ftc = F(r, c);
+                const float fk = a.f[j];
+                const float P = precond(a.pmode, fk, a.lam[j], lp, a.pbuf, j);
+                const float z = ftc - P * (gfs[tid] + gR);
+                const float fn = z > 0.0f ? z : 0.0f;
+                a.f[j] = fn;
+                a.ft_next[j] = fn + a.theta_next[0] * (fn - fk);
+                const double df = static_cast<double>(fn) - static_cast<double>(fk);
+                dd = df * df;
+                nn = static_cast<double>(fn) * static_cast<double>(fn);
+            }
         }
     }
     if (a.re_part) {
@@ -396,119 +487,126 @@ __global__ __launch_bounds__(256) void k_step_single(StepArgs a) {
 }
 
 // ------------------------------------------------------------------------
-// Step kernel, B > 1.  Tile of 4 x 4 pixels, 4 waves; wave w owns tile row w;
-// lanes = solves (64 per blockIdx.y chunk).
+// Step kernel, B > 1 (lane layout).  Tile of 4 x 4 pixels per workgroup of 16
+// waves, lanes = the 64 solves of chunk blockIdx.y: wave w back-projects pixel
+// w; the 8 x 8 halo of f~ is staged in LDS; the 36 weighted vectors of the
+// 6 x 6 block are computed once (waves 0..15 take positions w, w+16, w+32) and
+// kept in LDS; wave w combines them for pixel w and applies the update.
 // ------------------------------------------------------------------------
 
-template <typename IT, int VT>
-__global__ __launch_bounds__(256) void k_step_batch(StepArgs a) {
-    __shared__ float halo[64][64];
-    __shared__ double red[4][64][2];
+template <int VT>
+__global__ __launch_bounds__(1024, 8) void k_step_batch(StepArgs a) {
+    __shared__ float halo[64][64];      // reused for the RE partial sums at the end
+    __shared__ float pqs[6][36][64];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int N = a.n, B = a.B;
+    const int N = a.n;
+    const int d = N * N;
+    const int chunk = blockIdx.y;
+    const int b = chunk * 64 + lane;
+    const bool act = b < a.B;
     const int tiles_x = a.tiles_x, tiles_y = (N + 3) / 4;
     const int tile = tile_of(blockIdx.x, tiles_x, tiles_y, a.xcd_remap);
     const int r0 = (tile / tiles_x) * 4, c0 = (tile % tiles_x) * 4;
-    const int b = blockIdx.y * 64 + lane;
-    const bool act = b < B;
-    const int bl = act ? b : B - 1;  // idle lanes re-read a valid element (same cache line)
-    const IT *__restrict__ col = static_cast<const IT *>(a.col);
-    const float *__restrict__ e = a.e;
-    const int r = r0 + w;
+    const int r = r0 + (w >> 2), c = c0 + (w & 3);
+    const bool in = r < N && c < N;
+    const size_t vbase = static_cast<size_t>(chunk) * d * 64 + lane;
 
-    float gF[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (a.out_mode != SO_REG) {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int c = c0 + p;
-            if (r < N && c < N) {
-                const int j = r * N + c;
-                const int k0 = a.row_ptr[j], k1 = a.row_ptr[j + 1];
-                float acc = 0.0f;
-                for (int k = k0; k < k1; k += kChunk) {
-                    uint32_t cc[8];
-                    float v[8], ev[8];
-                    load_cols8<IT>(col, k, cc);
-                    load_vals8<VT>(a.val, k, v);
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) ev[t] = e[static_cast<size_t>(cc[t]) * B + bl];
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) acc = fmaf(v[t], ev[t], acc);
-                }
-                gF[p] = acc;
-            }
-        }
+    float gF = 0.0f;
+    if (a.out_mode != SO_REG && in) {
+        const int j = r * N + c;
+        const auto er = make_rsrc(reinterpret_cast<const char *>(a.e) + static_cast<size_t>(chunk) * a.m * 256,
+                                  256u * static_cast<uint32_t>(a.m));
+        const auto cr = make_rsrc(a.col32, 4u * static_cast<uint32_t>(a.nnz_padded));
+        const auto vr = make_rsrc(a.val, static_cast<uint32_t>(a.nnz_padded) * vbytes<VT>());
+        gF = gather_dot_lanes64<VT>(cr, vr, er, a.row_ptr[j], a.row_ptr[j + 1], 4u * lane);
     }
-    for (int q = w; q < 64; q += 4) {
+    for (int q = w; q < 64; q += 16) {
         const int hr = r0 - 2 + (q >> 3), hc = c0 - 2 + (q & 7);
         halo[q][lane] = (hr >= 0 && hr < N && hc >= 0 && hc < N)
-                            ? a.ft[static_cast<size_t>(hr * N + hc) * B + bl]
+                            ? a.ft[vbase + static_cast<size_t>(hr * N + hc) * 64]
                             : 0.0f;
     }
     __syncthreads();
-    double dd = 0.0, nn = 0.0;
-    if (act && r < N) {
-        const LaneParams lp = a.lp[b];
-        const float th = a.theta_next ? a.theta_next[b] : 0.0f;
-        auto F = [&](int rr, int cc) { return halo[(rr - r0 + 2) * 8 + (cc - c0 + 2)][lane]; };
+    const LaneParams lp = a.lp[b];
+    auto F = [&](int rr, int cc) { return halo[(rr - r0 + 2) * 8 + (cc - c0 + 2)][lane]; };
+    for (int q = w; q < 36; q += 16) {
+        const int rr = r0 - 1 + q / 6, cc = c0 - 1 + q % 6;
+        float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (rr >= 0 && rr < N && cc >= 0 && cc < N) pq6(F, rr, cc, N, lp.lambda1, lp.lambda2, lp.eps, o);
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int c = c0 + p;
-            if (c >= N) continue;
-            const size_t o = static_cast<size_t>(r * N + c) * B + b;
-            if (a.out_mode == SO_BACK) {
-                a.out[o] = gF[p];
-                continue;
-            }
-            const float gR = grad_reg_at(F, r, c, N, lp.lambda1, lp.lambda2, lp.eps);
+        for (int k = 0; k < 6; ++k) pqs[k][q][lane] = o[k];
+    }
+    __syncthreads();
+    const float ftc = in ? F(r, c) : 0.0f;
+    double dd = 0.0, nn = 0.0;
+    if (in) {
+        const size_t o = vbase + static_cast<size_t>(r * N + c) * 64;
+        auto Q = [&](int dr, int dc, int k) {
+            return pqs[k][(r - r0 + 1 + dr) * 6 + (c - c0 + 1 + dc)][lane];
+        };
+        if (a.out_mode == SO_BACK) {
+            a.out[o] = gF;
+        } else {
+            const float gR = combine_grad(Q, r, c, N);
             if (a.out_mode == SO_REG) {
                 a.out[o] = gR;
-                continue;
+            } else {
+                const float th = a.theta_next[b];
+                const float fk = a.f[o];
+                const float P = precond(a.pmode, fk, a.lam[r * N + c], lp, a.pbuf, o);
+                const float z = ftc - P * (gF + gR);
+                const float fn = z > 0.0f ? z : 0.0f;
+                a.f[o] = fn;
+                a.ft_next[o] = fn + th * (fn - fk);
+                const double df = static_cast<double>(fn) - static_cast<double>(fk);
+                dd = df * df;
+                nn = static_cast<double>(fn) * static_cast<double>(fn);
             }
-            const float ftc = F(r, c);
-            const float fk = a.f[o];
-            const float P = precond(a.pmode, fk, a.lam[r * N + c], lp, a.pbuf, o);
-            const float z = ftc - P * (gF[p] + gR);
-            const float fn = z > 0.0f ? z : 0.0f;
-            a.f[o] = fn;
-            a.ft_next[o] = fn + th * (fn - fk);
-            const double df = static_cast<double>(fn) - static_cast<double>(fk);
-            dd += df * df;
-            nn += static_cast<double>(fn) * static_cast<double>(fn);
         }
     }
     if (a.re_part) {
-        red[w][lane][0] = dd;
-        red[w][lane][1] = nn;
+        double *red = reinterpret_cast<double *>(&halo[0][0]);   // [16][64][2]
+        __syncthreads();                                          // halo no longer read
+        red[(w * 64 + lane) * 2] = dd;
+        red[(w * 64 + lane) * 2 + 1] = nn;
         __syncthreads();
         if (w == 0 && act) {
-            const double s0 = red[0][lane][0] + red[1][lane][0] + red[2][lane][0] + red[3][lane][0];
-            const double s1 = red[0][lane][1] + red[1][lane][1] + red[2][lane][1] + red[3][lane][1];
-            const size_t o = (static_cast<size_t>(blockIdx.x) * B + b) * 2;
-            a.re_part[o] = s0;
-            a.re_part[o + 1] = s1;
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                s0 += red[(q * 64 + lane) * 2];
+                s1 += red[(q * 64 + lane) * 2 + 1];
+            }
+            const size_t po = (static_cast<size_t>(blockIdx.x) * a.Bp + b) * 2;
+            a.re_part[po] = s0;
+            a.re_part[po + 1] = s1;
         }
     }
 }
 
 // ------------------------------------------------------------------------
 // FP64 monitoring reductions (deterministic: fixed per-block order, then a
-// fixed-order sum over blocks).
+// fixed-order sum over blocks).  Vectors in the layout of B (plain for B = 1,
+// lane layout otherwise); partials part[blk][Bp].
 // ------------------------------------------------------------------------
 
+__device__ __forceinline__ size_t vidx(int i, int b, int n, int B) {
+    return B == 1 ? static_cast<size_t>(i) : lidx(i, b, n);
+}
+
 // part[blk][b] = sum over rows of the block of (y - gamma) - g ln y  (y = A x + gamma).
-__global__ __launch_bounds__(256) void k_fidelity_terms(int m, int B, const float *y, const float *g,
-                                                        const float *gamma, const float *gamma_lane,
-                                                        double *part) {
+__global__ __launch_bounds__(256) void k_fidelity_terms(int m, int B, int Bp, const float *y,
+                                                        const float *g, const float *gamma,
+                                                        const float *gamma_lane, double *part) {
     __shared__ double red[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int b = blockIdx.y * 64 + lane;
     double s = 0.0;
     if (b < B) {
         for (int i = blockIdx.x * 4 + w; i < m; i += gridDim.x * 4) {
-            const size_t o = static_cast<size_t>(i) * B + b;
+            const size_t o = vidx(i, b, m, B);
             const double gam = gamma ? gamma[o] : (gamma_lane ? gamma_lane[b] : 0.0f);
             const double yy = y[o];
             s += yy - gam;
@@ -518,12 +616,12 @@ __global__ __launch_bounds__(256) void k_fidelity_terms(int m, int B, const floa
     red[w][lane] = s;
     __syncthreads();
     if (w == 0 && b < B)
-        part[static_cast<size_t>(blockIdx.x) * B + b] =
+        part[static_cast<size_t>(blockIdx.x) * Bp + b] =
             red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
 // part[blk][b] = lambda1 sum s_eps(u) + lambda2 sum s_eps(v) over the block's pixels (FP64).
-__global__ __launch_bounds__(256) void k_reg_value(int n, int B, const float *x,
+__global__ __launch_bounds__(256) void k_reg_value(int n, int B, int Bp, const float *x,
                                                    const LaneParams *lp, double *part) {
     __shared__ double red[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -533,7 +631,7 @@ __global__ __launch_bounds__(256) void k_reg_value(int n, int B, const float *x,
     if (b < B) {
         const LaneParams p = lp[b];
         const double eps = p.eps;
-        auto F = [&](int rr, int cc) { return x[static_cast<size_t>(rr * n + cc) * B + b]; };
+        auto F = [&](int rr, int cc) { return x[vidx(rr * n + cc, b, d, B)]; };
         for (int j = blockIdx.x * 4 + w; j < d; j += gridDim.x * 4) {
             float o[6];
             uv6(F, j / n, j % n, n, o);
@@ -549,12 +647,12 @@ __global__ __launch_bounds__(256) void k_reg_value(int n, int B, const float *x,
     red[w][lane] = s;
     __syncthreads();
     if (w == 0 && b < B)
-        part[static_cast<size_t>(blockIdx.x) * B + b] =
+        part[static_cast<size_t>(blockIdx.x) * Bp + b] =
             red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
 // part[blk][b] = sum over the block's rows of g - gamma (for ACTc of the initial image).
-__global__ __launch_bounds__(256) void k_sum_g_minus_gamma(int m, int B, const float *g,
+__global__ __launch_bounds__(256) void k_sum_g_minus_gamma(int m, int B, int Bp, const float *g,
                                                            const float *gamma,
                                                            const float *gamma_lane, double *part) {
     __shared__ double red[4][64];
@@ -563,7 +661,7 @@ __global__ __launch_bounds__(256) void k_sum_g_minus_gamma(int m, int B, const f
     double s = 0.0;
     if (b < B) {
         for (int i = blockIdx.x * 4 + w; i < m; i += gridDim.x * 4) {
-            const size_t o = static_cast<size_t>(i) * B + b;
+            const size_t o = vidx(i, b, m, B);
             const double gam = gamma ? gamma[o] : (gamma_lane ? gamma_lane[b] : 0.0f);
             s += static_cast<double>(g[o]) - gam;
         }
@@ -571,51 +669,81 @@ __global__ __launch_bounds__(256) void k_sum_g_minus_gamma(int m, int B, const f
     red[w][lane] = s;
     __syncthreads();
     if (w == 0 && b < B)
-        part[static_cast<size_t>(blockIdx.x) * B + b] =
+        part[static_cast<size_t>(blockIdx.x) * Bp + b] =
             red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
-// out[b*ncomp + c] = sum_blk part[(blk*B + b)*ncomp + c], blocks in order.
-__global__ void k_reduce_partials(const double *part, int nblocks, int B, int ncomp, double *out) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= B * ncomp) return;
+// out[b*ncomp + c] = sum_blk part[(blk*Bp + b)*ncomp + c] for b < B: one wave
+// per output, lane l sums blocks l, l+64, ... in order, then a fixed xor tree.
+__global__ __launch_bounds__(64) void k_reduce_partials(const double *part, int nblocks, int B,
+                                                        int Bp, int ncomp, double *out) {
+    const int t = blockIdx.x;
     const int b = t / ncomp, c = t % ncomp;
+    if (b >= B) return;
+    const int lane = threadIdx.x;
     double s = 0.0;
-    for (int k = 0; k < nblocks; ++k) s += part[(static_cast<size_t>(k) * B + b) * ncomp + c];
-    out[t] = s;
+    for (int k = lane; k < nblocks; k += 64) s += part[(static_cast<size_t>(k) * Bp + b) * ncomp + c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[t] = s;
 }
 
 // ------------------------------------------------------------------------
-// Layout and initialisation helpers.
+// Layout conversion and initialisation helpers.
 // ------------------------------------------------------------------------
 
-// out[c][r] = in[r][c] for an rows x cols array (32 x 32 LDS tiles).
-__global__ __launch_bounds__(256) void k_transpose(const float *in, float *out, int rows, int cols) {
+// Solve-major in[b][i] (B rows of n) -> lane layout; padding lanes get 0.
+// Grid: (ceil(n/32), 2, chunks); 32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void k_to_lanes(const float *in, float *out, int n, int B) {
     __shared__ float t[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int i0 = blockIdx.x * 32, l0 = blockIdx.y * 32, chunk = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int k = ty; k < 32; k += 8) {
-        const int r = by + k, c = bx + tx;
-        if (r < rows && c < cols) t[k][tx] = in[static_cast<size_t>(r) * cols + c];
+        const int b = chunk * 64 + l0 + k, i = i0 + tx;
+        t[k][tx] = (b < B && i < n) ? in[static_cast<size_t>(b) * n + i] : 0.0f;
     }
     __syncthreads();
     for (int k = ty; k < 32; k += 8) {
-        const int c = bx + k, r = by + tx;
-        if (r < rows && c < cols) out[static_cast<size_t>(c) * rows + r] = t[tx][k];
+        const int i = i0 + k, l = l0 + tx;
+        if (i < n) out[(static_cast<size_t>(chunk) * n + i) * 64 + l] = t[tx][k];
     }
 }
 
-// Initial image of Section 4.1: TMC * 1_disk (disk of radius N/2 about the centre).
-__global__ void k_disk_init(int n, int B, const double *tmc, float *f, float *ft) {
+// Lane layout -> solve-major out[b][i] for b < B.
+__global__ __launch_bounds__(256) void k_from_lanes(const float *in, float *out, int n, int B) {
+    __shared__ float t[32][33];
+    const int i0 = blockIdx.x * 32, l0 = blockIdx.y * 32, chunk = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {
+        const int i = i0 + k;
+        t[k][tx] = i < n ? in[(static_cast<size_t>(chunk) * n + i) * 64 + l0 + tx] : 0.0f;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int b = chunk * 64 + l0 + k, i = i0 + tx;
+        if (b < B && i < n) out[static_cast<size_t>(b) * n + i] = t[tx][k];
+    }
+}
+
+// Initial image of Section 4.1: TMC * 1_disk (disk of radius N/2 about the
+// centre) in the layout of B; padding lanes 0.
+__global__ void k_disk_init(int n, int B, int Bp, const double *tmc, float *f, float *ft) {
     const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const size_t total = static_cast<size_t>(n) * n * B;
-    if (t >= total) return;
-    const int b = static_cast<int>(t % B);
-    const int j = static_cast<int>(t / B);
+    const size_t d = static_cast<size_t>(n) * n;
+    if (t >= d * Bp) return;
+    int j, b;
+    if (B == 1) {
+        j = static_cast<int>(t);
+        b = 0;
+    } else {
+        const size_t chunk = t / (d * 64), rem = t % (d * 64);
+        j = static_cast<int>(rem / 64);
+        b = static_cast<int>(chunk * 64 + rem % 64);
+    }
     const int r = j / n, c = j % n;
     const double ctr = (n - 1) / 2.0, rad = n / 2.0;
     const bool in = (c - ctr) * (c - ctr) + (r - ctr) * (r - ctr) <= rad * rad;
-    const float v = in ? static_cast<float>(tmc[b]) : 0.0f;
+    const float v = (in && b < B) ? static_cast<float>(tmc[b]) : 0.0f;
     f[t] = v;
     ft[t] = v;
 }
@@ -626,9 +754,11 @@ __global__ void k_fill(float *p, size_t n, float v) {
 }
 
 // e[i][b] *= scale[i] (a residual handed to the FP8 transpose, which has no row scales).
-__global__ void k_scale_rows(float *e, const float *scale, int m, int B) {
+__global__ void k_scale_rows(float *e, const float *scale, int m, int B, int Bp) {
     const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t < static_cast<size_t>(m) * B) e[t] *= scale[t / B];
+    if (t >= static_cast<size_t>(m) * Bp) return;
+    const int i = B == 1 ? static_cast<int>(t) : static_cast<int>((t / 64) % m);
+    e[t] *= scale[i];
 }
 
 __global__ void k_copy(float *dst, const float *src, size_t n) {
@@ -643,7 +773,7 @@ __global__ void k_copy(float *dst, const float *src, size_t n) {
 namespace {
 
 template <typename IT, int VT>
-hipError_t fwd_dispatch_g(const FwdArgs &a, int group, hipStream_t st) {
+hipError_t fwd_dispatch(const FwdArgs &a, int group, hipStream_t st) {
     if (a.B == 1) {
         switch (group) {
 #define APPGA_FWD_CASE(GG)                                                                       \
@@ -663,20 +793,20 @@ hipError_t fwd_dispatch_g(const FwdArgs &a, int group, hipStream_t st) {
                 return hipErrorInvalidValue;
         }
     } else {
-        hipLaunchKernelGGL((k_fwd_batch<IT, VT>), dim3((a.m + 3) / 4, (a.B + 63) / 64), dim3(256),
-                           0, st, a);
+        const int wgs = std::min((a.m + 3) / 4, a.fwd_wgs > 0 ? a.fwd_wgs : 2048);
+        hipLaunchKernelGGL((k_fwd_batch<VT>), dim3(wgs, a.Bp / 64), dim3(256), 0, st, a);
     }
     return hipGetLastError();
 }
 
 template <typename IT, int VT>
-hipError_t step_dispatch_g(const StepArgs &a, int group, hipStream_t st) {
+hipError_t step_dispatch(const StepArgs &a, int group, hipStream_t st) {
     const int tiles = ((a.n + 3) / 4) * ((a.n + 3) / 4);
     if (a.B == 1) {
         switch (group) {
-#define APPGA_STEP_CASE(GG)                                                                   \
-    case GG:                                                                                  \
-        hipLaunchKernelGGL((k_step_single<IT, VT, GG>), dim3(tiles), dim3(256), 0, st, a);    \
+#define APPGA_STEP_CASE(GG)                                                                    \
+    case GG:                                                                                   \
+        hipLaunchKernelGGL((k_step_single<IT, VT, GG>), dim3(tiles), dim3(16 * GG), 0, st, a); \
         break;
             APPGA_STEP_CASE(4)
             APPGA_STEP_CASE(8)
@@ -688,8 +818,7 @@ hipError_t step_dispatch_g(const StepArgs &a, int group, hipStream_t st) {
                 return hipErrorInvalidValue;
         }
     } else {
-        hipLaunchKernelGGL((k_step_batch<IT, VT>), dim3(tiles, (a.B + 63) / 64), dim3(256), 0, st,
-                           a);
+        hipLaunchKernelGGL((k_step_batch<VT>), dim3(tiles, a.Bp / 64), dim3(1024), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -714,19 +843,23 @@ hipError_t by_type(int idx16, int vtype, F &&f) {
     return hipErrorInvalidValue;
 }
 
+unsigned blocks_for(size_t n) { return static_cast<unsigned>((n + 255) / 256); }
+
 }  // namespace
 
 hipError_t launch_forward(const DevCsr &A, const FwdArgs &args, int group, hipStream_t st) {
     return by_type(A.idx16, A.vtype, [&](auto it, auto vt) {
-        return fwd_dispatch_g<decltype(it), decltype(vt)::value>(args, group, st);
+        return fwd_dispatch<decltype(it), decltype(vt)::value>(args, group, st);
     });
 }
 
 hipError_t launch_step(const DevCsr &AT, const StepArgs &args, int group, hipStream_t st) {
     return by_type(AT.idx16, AT.vtype, [&](auto it, auto vt) {
-        return step_dispatch_g<decltype(it), decltype(vt)::value>(args, group, st);
+        return step_dispatch<decltype(it), decltype(vt)::value>(args, group, st);
     });
 }
+
+int pad_lanes(int B) { return B == 1 ? 1 : (B + 63) / 64 * 64; }
 
 int step_blocks(int n, int B) {
     (void)B;
@@ -740,64 +873,67 @@ int sum_blocks(int m) { return fidelity_blocks(m); }
 hipError_t launch_fidelity_terms(int m, int B, const float *y, const float *g, const float *gamma,
                                  const float *gamma_lane, double *part, hipStream_t st) {
     hipLaunchKernelGGL(k_fidelity_terms, dim3(fidelity_blocks(m), (B + 63) / 64), dim3(256), 0, st,
-                       m, B, y, g, gamma, gamma_lane, part);
+                       m, B, pad_lanes(B), y, g, gamma, gamma_lane, part);
     return hipGetLastError();
 }
 
 hipError_t launch_reg_value(int n, int B, const float *x, const LaneParams *lp, double *part,
                             hipStream_t st) {
     hipLaunchKernelGGL(k_reg_value, dim3(reg_value_blocks(n), (B + 63) / 64), dim3(256), 0, st, n,
-                       B, x, lp, part);
+                       B, pad_lanes(B), x, lp, part);
     return hipGetLastError();
 }
 
 hipError_t launch_sum_g_minus_gamma(int m, int B, const float *g, const float *gamma,
                                     const float *gamma_lane, double *part, hipStream_t st) {
     hipLaunchKernelGGL(k_sum_g_minus_gamma, dim3(sum_blocks(m), (B + 63) / 64), dim3(256), 0, st,
-                       m, B, g, gamma, gamma_lane, part);
+                       m, B, pad_lanes(B), g, gamma, gamma_lane, part);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(const double *part, int nblocks, int B, int ncomp, double *out,
                                   hipStream_t st) {
-    const int t = B * ncomp;
-    hipLaunchKernelGGL(k_reduce_partials, dim3((t + 127) / 128), dim3(128), 0, st, part, nblocks,
-                       B, ncomp, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(B * ncomp), dim3(64), 0, st, part, nblocks, B,
+                       pad_lanes(B), ncomp, out);
     return hipGetLastError();
 }
 
-hipError_t launch_transpose(const float *in, float *out, int rows, int cols, hipStream_t st) {
-    hipLaunchKernelGGL(k_transpose, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, st, in,
-                       out, rows, cols);
+hipError_t launch_to_lanes(const float *in, float *out, int n, int B, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_lanes, dim3((n + 31) / 32, 2, (B + 63) / 64), dim3(256), 0, st, in, out,
+                       n, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_lanes(const float *in, float *out, int n, int B, hipStream_t st) {
+    hipLaunchKernelGGL(k_from_lanes, dim3((n + 31) / 32, 2, (B + 63) / 64), dim3(256), 0, st, in,
+                       out, n, B);
     return hipGetLastError();
 }
 
 hipError_t launch_disk_init(int n, int B, const double *tmc, float *f, float *ft, hipStream_t st) {
-    const size_t total = static_cast<size_t>(n) * n * B;
-    hipLaunchKernelGGL(k_disk_init, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
-                       st, n, B, tmc, f, ft);
+    const size_t total = static_cast<size_t>(n) * n * pad_lanes(B);
+    hipLaunchKernelGGL(k_disk_init, dim3(blocks_for(total)), dim3(256), 0, st, n, B, pad_lanes(B),
+                       tmc, f, ft);
     return hipGetLastError();
 }
 
 hipError_t launch_fill(float *p, size_t n, float v, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, p, n,
-                       v);
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, st, p, n, v);
     return hipGetLastError();
 }
 
 hipError_t launch_scale_rows(float *e, const float *scale, int m, int B, hipStream_t st) {
-    const size_t n = static_cast<size_t>(m) * B;
+    const size_t n = static_cast<size_t>(m) * pad_lanes(B);
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scale_rows, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
-                       e, scale, m, B);
+    hipLaunchKernelGGL(k_scale_rows, dim3(blocks_for(n)), dim3(256), 0, st, e, scale, m, B,
+                       pad_lanes(B));
     return hipGetLastError();
 }
 
 hipError_t launch_copy(float *dst, const float *src, size_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, dst,
-                       src, n);
+    hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(256), 0, st, dst, src, n);
     return hipGetLastError();
 }
 
