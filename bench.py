@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=300)
     ap.add_argument("--profile", action="store_true",
                     help="short run for profilers: no CPU baseline, no plain path")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="serving leg: requests (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=1000.0,
+                    help="serving leg: mean Poisson arrival rate, requests/s")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also launch a plain device copy of MIB MiB (5 times) so that a "
                          "profiler's FETCH_SIZE/WRITE_SIZE can be scaled by a known size")
@@ -90,6 +94,52 @@ def cpu_baseline(pr, n_iters: int):
                 kind="oracle",
                 sample="%d of the 64 sinograms x %d iterations, one solve per thread, FP64, "
                        "%.1f s wall" % (cores, n_iters, dt))
+
+
+def serve_leg(ap, synth, ctx, mat128, pr128, n_req: int, rate: float):
+    """Continuous batching: Poisson arrivals of 64x64 (96 x 90, FP32 matrix) and
+    128x128 (the bench matrix) requests, lambda ~ U[0.005, 0.1], omega in
+    {0.3, 0.6, 1.0}, iteration budgets ~ U{50..300}.  Latency = completion -
+    submission, measured by the server."""
+    geom64 = synth.Geometry(64, 96, 90)
+    pr64 = synth.make_problem(geom64, list(range(500, 516)), tc_range=(1e5, 1e7),
+                              rf_range=(0.05, 0.2))
+    mat64 = ap.load_matrix(ctx, pr64.A, geom64, "f32")
+    rng = np.random.default_rng(2024)
+    reqs = []
+    for i in range(n_req):
+        small = rng.random() < 0.5
+        pr, mat = (pr64, mat64) if small else (pr128, mat128)
+        b = int(rng.integers(0, len(pr.seeds)))
+        p = ap.make_params(lam=float(rng.uniform(0.005, 0.1)), eps=1e-3,
+                           omega=float(rng.choice([0.3, 0.6, 1.0])),
+                           iterations=int(rng.integers(50, 301)))
+        reqs.append((pr, mat, b, p, float(rng.exponential(1.0 / rate))))
+    srv = ap.appga_server_start(ctx, 8 << 30, 64)
+    tickets = []
+    t0 = time.perf_counter()
+    t_next = t0
+    for pr, mat, b, p, gap in reqs:
+        t_next += gap
+        while time.perf_counter() < t_next:
+            pass
+        tickets.append((ap.appga_submit(srv, mat, pr.g[b], pr.gamma[b], p), pr.geom.d, p.iterations))
+    lat, iters = [], 0
+    for t, d, k in tickets:
+        _, st = ap.appga_wait(srv, t, d, 120000)
+        lat.append(st["seconds"])
+        iters += k
+    dt = time.perf_counter() - t0
+    ap.appga_server_stop(srv)
+    ap.appga_free_system_matrix(ctx, mat64)
+    lat = np.asarray(lat) * 1e3
+    return dict(requests=n_req, offered_rate=rate, throughput_req_s=round(n_req / dt, 1),
+                solve_iterations_per_s=round(iters / dt, 1),
+                p50_ms=round(float(np.percentile(lat, 50)), 3),
+                p99_ms=round(float(np.percentile(lat, 99)), 3),
+                mean_iterations=round(iters / n_req, 1),
+                mix="50% 64x64 (96x90, FP32 matrix) / 50% 128x128 (200x168, bench matrix), "
+                    "lambda U[0.005,0.1], omega {0.3,0.6,1.0}, iterations U{50..300}")
 
 
 def main():
@@ -192,6 +242,11 @@ def main():
                      ms_per_iter=round(1e3 * dt1 / args.plain_steps, 4),
                      path="single-solve FP32 matrix, the 64 solves one after another")
 
+    serving = None
+    if args.serve_requests > 0 and not args.profile:
+        log("serving leg: %d requests at %.0f/s" % (args.serve_requests, args.serve_rate))
+        serving = serve_leg(ap, synth, ctx, mat, pr, args.serve_requests, args.serve_rate)
+
     cpu = None
     if not args.no_cpu_baseline and not args.profile:
         log("timing the FP64 oracle on the host cores")
@@ -223,6 +278,7 @@ def main():
                         for kk, vv in v.items()} for k, v in kernels.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
         "matrix_bytes": info,
         "objective_lane0": stats[0]["objective"],
     }

@@ -476,8 +476,10 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
     HIP_TRY(hipSetDevice(ctx->device));
     const int vtype = static_cast<int>(storage);
 
+    static std::atomic<uint64_t> next_serial{1};
     auto *mat = new appga_matrix();
     mat->ctx = ctx;
+    mat->serial = next_serial.fetch_add(1);
     mat->geom = *geom;
     mat->nnz = nnz;
     mat->storage = vtype;

@@ -40,6 +40,7 @@ struct appga_matrix {
     int xcd_remap = 0;
     int fwd_wgs = 2048;                // batched forward: workgroups of the row-strided grid
     mutable std::atomic<int> inflight{0};
+    uint64_t serial = 0;               // unique per load (servers key their pools by it)
 };
 
 struct appga_solve {
