@@ -220,30 +220,54 @@ appga_status appga_set_kernel_timing(appga_ctx *ctx, int32_t enable);
 appga_status appga_kernel_times(appga_ctx *ctx, int32_t cap, char *names_out, int32_t names_cap,
                                 int64_t *counts, double *total_ms, int32_t *n_kernels);
 
-/* Serving: a continuous-batching request loop on one device.
- * hbm_budget_bytes bounds the device memory of admitted requests (iterates,
- * momentum state, data and ratio buffers); slots_per_matrix bounds the
- * requests advanced together per system matrix.  Requests are admitted as
- * they arrive while footprint and slots allow; all admitted requests of a
- * matrix are advanced together one iteration per step, each from its own
- * iteration counter, and leave as soon as their budget is done. */
+/* Serving: a continuous-batching request loop on one device (Algorithm 1 per
+ * request; Section 4.1 initial image; EM preconditioner, eq. EM; momentum by
+ * eq. GNtheta from each request's own iteration counter).
+ *
+ * One loop thread owns all device work.  Per loaded system matrix it keeps a
+ * pool of 64 lanes in device memory (data, background, f, two f~ buffers and
+ * the ratio residual per lane: 4*64*(3m + 3d) bytes plus under 64 KiB) and
+ * advances every occupied lane of a pool by one iteration per step, replayed
+ * from captured hipGraphs on the pool's own stream.  A request is admitted as
+ * soon as its pool has a free lane among the first slots_per_matrix (1..64)
+ * and, for a pool not yet present, the pools' total footprint stays within
+ * hbm_budget_bytes (idle pools of other matrices are freed to make room); it
+ * leaves after exactly params->iterations iterations.  A served result equals
+ * the result of the same request in appga_reconstruct_batch bit for bit (the
+ * lanes never interact).  The system matrices are the caller's: they are not
+ * counted in the budget and must stay loaded (appga_free_system_matrix returns
+ * APPGA_E_BUSY while requests on them are in flight). */
 typedef struct {
     int64_t hbm_budget_bytes;
     int32_t slots_per_matrix;
     int32_t reserved;
 } appga_server_cfg;
 
+/* Starts the loop thread.  APPGA_E_INVALID_ARG for NULL arguments or a
+ * non-positive budget or slot count. */
 appga_status appga_server_start(appga_ctx *ctx, const appga_server_cfg *cfg, appga_server **out);
-/* Thread-safe.  Copies g (m), gamma (m, or NULL = params->gamma_scalar) and
- * *params; the request uses the paper's initial image.  *ticket identifies it. */
+/* Thread-safe.  Copies g (m host floats), gamma (m host floats, or NULL =
+ * params->gamma_scalar in every bin) and *params; *ticket identifies the
+ * request.  Errors (nothing queued): APPGA_E_INVALID_ARG (NULL argument, a
+ * matrix of another context, a preconditioner other than EM, a stopping
+ * server); APPGA_E_DOMAIN (parameters outside the method's domain, iterations
+ * < 1, ACTc = sum(g) - sum(gamma) <= 0); APPGA_E_NONFINITE (NaN/Inf in g or
+ * gamma); APPGA_E_OOM (this matrix's pool alone exceeds the budget). */
 appga_status appga_submit(appga_server *srv, const appga_matrix *mat, const float *g,
                           const float *gamma, const appga_params *params, uint64_t *ticket);
 /* Thread-safe.  Waits up to timeout_ms (< 0 = forever) for the ticket, then
- * copies f^{K+1} (d floats) and its stats and forgets the ticket.  stats->seconds
- * is the latency from submission to completion. */
+ * copies f^{K+1} into f_out (host, n*n floats of the request's matrix, row
+ * major) and the stats into *stats (either may be NULL), and forgets the
+ * ticket.  stats->seconds is the latency from submission to completion and
+ * guard_clamps the floored bins of the request; objective0, objective and re
+ * are not monitored by the server (0).  Errors: APPGA_E_NOT_FOUND (unknown or
+ * already collected ticket), APPGA_E_TIMEOUT (still running; wait again),
+ * APPGA_E_NONFINITE (the result holds NaN/Inf; it is copied out), or the
+ * device error that ended the request. */
 appga_status appga_wait(appga_server *srv, uint64_t ticket, float *f_out, appga_stats *stats,
                         int32_t timeout_ms);
-/* Stops admitting, finishes in-flight work, joins the loop and frees the server. */
+/* Stops admitting, finishes every queued and running request (their tickets
+ * can no longer be collected), joins the loop and frees the server. */
 appga_status appga_server_stop(appga_server *srv);
 
 /* Message describing the calling thread's most recent failure ("" if none). */

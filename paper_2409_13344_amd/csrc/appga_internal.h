@@ -81,11 +81,6 @@ struct FwdArgs {
     int mode;               // FwdMode
     int scale_out;          // FM_RATIO with FP8: write row_scale[i] * e_i (the transpose has no scales)
     int fwd_wgs;            // B > 1: workgroups of the row-strided grid (0 = default)
-    // Serving (or null): block 0 advances the per-lane iteration counter k and
-    // writes theta_{k+1} (eq. GNtheta, FP64) for the step kernel of the same iteration.
-    int *lane_k;            // [64] per-lane k
-    const double *lane_mom; // [64][4] per lane {a, b, omega, momentum_none}
-    float *lane_theta;      // [64] theta_{k+1} out
     unsigned long long *clamps;  // floored-bin counter (may be null)
 };
 
@@ -117,6 +112,9 @@ struct StepArgs {
 };
 
 // Serving helpers (kernels.hip).
+// Serving: advances the 64 per-lane iteration counters k by one and writes
+// theta_{k+1} (eq. GNtheta, FP64) per lane; mom holds {a, b, omega, momentum_none}.
+hipError_t launch_lane_theta(int *lane_k, const double *mom, float *theta, hipStream_t st);
 hipError_t launch_lane_scatter(const float *src, float *dst, int n, int lane, hipStream_t st);
 hipError_t launch_lane_fill(float *dst, int n, int lane, float v, hipStream_t st);
 hipError_t launch_lane_gather(const float *src, float *dst, int n, int lane, hipStream_t st);

@@ -277,15 +277,6 @@ __global__ __launch_bounds__(256) void k_fwd_batch(FwdArgs a) {
     const int b = chunk * 64 + lane;
     const auto xr = make_rsrc(reinterpret_cast<const char *>(a.x) + static_cast<size_t>(chunk) * a.n_x * 256,
                               256u * static_cast<uint32_t>(a.n_x));
-    if (a.lane_k && blockIdx.x == 0 && threadIdx.x < 64) {
-        // theta_{k+1} = (t_k - 1) / t_{k+1}, t_k = a k^omega + b (eq. GNtheta), FP64
-        const int k = a.lane_k[b] + 1;
-        a.lane_k[b] = k;
-        const double *mm = a.lane_mom + 4 * b;
-        const double tk = mm[0] * pow(static_cast<double>(k), mm[2]) + mm[1];
-        const double tk1 = mm[0] * pow(static_cast<double>(k) + 1.0, mm[2]) + mm[1];
-        a.lane_theta[b] = mm[3] != 0.0 ? 0.0f : static_cast<float>((tk - 1.0) / tk1);
-    }
     const float gl = a.gamma_lane ? a.gamma_lane[b] : 0.0f;
     const auto cr = make_rsrc(a.col32, 4u * static_cast<uint32_t>(a.nnz_padded));
     const auto vr = make_rsrc(a.val, static_cast<uint32_t>(a.nnz_padded) * vbytes<VT>());
@@ -779,6 +770,18 @@ __global__ void k_copy(float *dst, const float *src, size_t n) {
 // Serving: single-lane transfers in a one-chunk lane layout.
 // ------------------------------------------------------------------------
 
+// theta_{k+1} = (t_k - 1) / t_{k+1}, t_k = a k^omega + b (eq. GNtheta), FP64,
+// after advancing k; one thread per lane.
+__global__ void k_lane_theta(int *lane_k, const double *mom, float *theta) {
+    const int b = threadIdx.x;
+    const int k = lane_k[b] + 1;
+    lane_k[b] = k;
+    const double *mm = mom + 4 * b;
+    const double tk = mm[0] * pow(static_cast<double>(k), mm[2]) + mm[1];
+    const double tk1 = mm[0] * pow(static_cast<double>(k) + 1.0, mm[2]) + mm[1];
+    theta[b] = mm[3] != 0.0 ? 0.0f : static_cast<float>((tk - 1.0) / tk1);
+}
+
 __global__ void k_lane_scatter(const float *src, float *dst, int n, int lane) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[static_cast<size_t>(i) * 64 + lane] = src[i];
@@ -968,6 +971,11 @@ hipError_t launch_scale_rows(float *e, const float *scale, int m, int B, hipStre
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scale_rows, dim3(blocks_for(n)), dim3(256), 0, st, e, scale, m, B,
                        pad_lanes(B));
+    return hipGetLastError();
+}
+
+hipError_t launch_lane_theta(int *lane_k, const double *mom, float *theta, hipStream_t st) {
+    hipLaunchKernelGGL(k_lane_theta, dim3(1), dim3(64), 0, st, lane_k, mom, theta);
     return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ struct Pool {
     int lane_done_iters[kLanes] = {};
     int64_t lane_clamps_base[kLanes] = {};
     std::deque<hipEvent_t> inflight;                  // events of launched steps
+    int pending_out = 0;                              // result copies not yet completed
     Clock::time_point idle_since = Clock::now();
 };
 
@@ -81,6 +82,7 @@ struct Extraction {
     unsigned long long *h_clamps = nullptr;
     hipEvent_t ev = nullptr;
     int lane = 0;
+    int d = 0;                       // image size of the request's matrix
 };
 
 }  // namespace
@@ -172,9 +174,6 @@ hipError_t capture_step(Pool *p, int cur, hipGraphExec_t *out) {
     fa.mode = FM_RATIO;
     fa.scale_out = 1;
     fa.fwd_wgs = mat->fwd_wgs;
-    fa.lane_k = p->lane_k;
-    fa.lane_mom = p->mom;
-    fa.lane_theta = p->theta;
     fa.clamps = p->clamps;
     StepArgs sa{};
     sa.row_ptr = mat->AT.row_ptr;
@@ -203,7 +202,8 @@ hipError_t capture_step(Pool *p, int cur, hipGraphExec_t *out) {
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t e1 = launch_forward(mat->A, fa, mat->group_fwd, p->stream);
+    hipError_t e1 = launch_lane_theta(p->lane_k, p->mom, p->theta, p->stream);
+    if (e1 == hipSuccess) e1 = launch_forward(mat->A, fa, mat->group_fwd, p->stream);
     hipError_t e2 = e1 == hipSuccess ? launch_step(mat->AT, sa, mat->group_back, p->stream) : e1;
     e = hipStreamEndCapture(p->stream, &graph);
     if (e1 != hipSuccess) return e1;
@@ -338,6 +338,9 @@ bool pool_active(const Pool *p) {
     return false;
 }
 
+// A pool may be freed only when no lane is occupied and no result copy reads it.
+bool pool_idle(const Pool *p) { return !pool_active(p) && p->pending_out == 0; }
+
 void finish(appga_server *srv, const std::shared_ptr<Request> &r, appga_status st) {
     r->mat->inflight.fetch_sub(1);
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -370,7 +373,7 @@ bool loop_pass(appga_server *srv) {
             if (srv->bytes_in_use + pool_bytes(mat) > srv->cfg.hbm_budget_bytes) {
                 // make room: free idle pools of other matrices
                 for (auto pit = srv->pools.begin(); pit != srv->pools.end();) {
-                    if (!pool_active(pit->second.get())) {
+                    if (pool_idle(pit->second.get())) {
                         srv->bytes_in_use -= pit->second->bytes;
                         destroy_pool(pit->second.get());
                         pit = srv->pools.erase(pit);
@@ -440,6 +443,7 @@ bool loop_pass(appga_server *srv) {
             x.pool = p;
             x.lane = l;
             const int d = p->mat->A.n_cols;
+            x.d = d;
             hipError_t ee = hipHostMalloc(reinterpret_cast<void **>(&x.h_out), sizeof(float) * d + 64,
                                           hipHostMallocDefault);
             x.h_clamps = reinterpret_cast<unsigned long long *>(x.h_out + d + (d & 1));
@@ -455,6 +459,7 @@ bool loop_pass(appga_server *srv) {
                 finish(srv, r, fail(APPGA_E_DEVICE, "result copy failed: %s", hipGetErrorString(ee)));
                 if (x.h_out) hipHostFree(x.h_out);
             } else {
+                ++p->pending_out;
                 srv->extractions.push_back(x);
             }
             r.reset();  // lane reusable (stream order protects the copy)
@@ -467,7 +472,8 @@ bool loop_pass(appga_server *srv) {
             ++i;
             continue;
         }
-        const int d = x.pool->mat->A.n_cols;
+        const int d = x.d;
+        --x.pool->pending_out;
         auto r = x.req;
         r->result.assign(x.h_out, x.h_out + d);
         r->stats.iterations_done = r->p.iterations;
