@@ -13,7 +13,7 @@
  * fixed points, count preservation, KKT at the minimiser of long runs,
  * Lemma 5 / Proposition 6 step inequalities, nonexpansiveness).
  *
- * Readings of points the paper leaves open (each also listed in the design doc):
+ * Readings of points the paper leaves open:
  *  - the first row of D is zero (D_11 = 0), so B annihilates constants;
  *  - image index j = r*N + c (row-major), Kronecker X (x) Y acts as X along r
  *    and Y along c; the objective is invariant under the other ordering;

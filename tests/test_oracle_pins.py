@@ -310,6 +310,14 @@ def test_identity_system():
     out = oracle.appga(A, n, 1, g, gam, 0.0, 0.0, 1e-3, 1.0, 2, f_init=f1)["f"]
     np.testing.assert_allclose(out, ref, rtol=1e-14)
     assert np.abs(out - g).max() > 1e-3         # momentum moves it off the fixed point
+    # monitors on the fixed point: RE(2) = ||g - f^1|| / ||g||, then exactly 0;
+    # Phi(f^1) and Phi(g) in closed form (gamma = 0, lambda = 0)
+    h = oracle.appga(A, n, 1, g, gam, 0.0, 0.0, 1e-3, 1.0, 4, momentum=oracle.MOMENTUM_NONE,
+                     f_init=f1, history=True)
+    assert abs(h["re"][0] - np.linalg.norm(g - f1) / np.linalg.norm(g)) <= 1e-15
+    assert np.all(h["re"][1:] == 0.0)
+    assert abs(h["obj"][0] - np.sum(f1 - g * np.log(f1))) <= 1e-13 * np.abs(h["obj"][0])
+    assert abs(h["obj"][-1] - np.sum(g - g * np.log(g))) <= 1e-13 * np.abs(h["obj"][-1])
 
 
 def test_floor_rule_identity_system():
