@@ -70,10 +70,12 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=2000)
     ap.add_argument("--profile", action="store_true",
                     help="short run for profilers: no CPU baseline, no plain path")
-    ap.add_argument("--serve-requests", type=int, default=512,
-                    help="serving leg: requests (0 = skip)")
-    ap.add_argument("--serve-rate", type=float, default=1000.0,
-                    help="serving leg: mean Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="serving leg: requests per rate (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, nargs="+", default=[200.0],
+                    help="serving leg: mean Poisson arrival rates, requests/s (several = a sweep)")
+    ap.add_argument("--no-projector", action="store_true",
+                    help="skip the single-solve projector leg on the 256^2 geometry")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also launch a plain device copy of MIB MiB (5 times) so that a "
                          "profiler's FETCH_SIZE/WRITE_SIZE can be scaled by a known size")
@@ -90,7 +92,13 @@ def kernel_bytes(kind: str, nnz: int, m: int, d: int, B: int, s_val: int, s_idx:
     if kind == "forward":
         # matrix + row_ptr + x (d x B) + g (m x B) + e (m x B, written); scalar background
         return nnz * (s_val + s_idx) + (m + 1) * 4 + 4 * B * (d + 2 * m)
-    # step: transpose + row_ptr + e (m x B) + ft (d x B) + f read/write + ft_next + Lambda
+    if kind == "back":
+        # transpose entries (value + slot index) + e (m x B) + A^T e (d x B, written)
+        return nnz * (s_val + s_idx) + 4 * B * (m + d)
+    if kind == "update":
+        # A^T e + ft + f read/write + ft_next (each d x B) + Lambda
+        return 4 * B * 5 * d + 4 * d
+    # fused step: transpose + row_ptr + e (m x B) + ft (d x B) + f read/write + ft_next + Lambda
     return nnz * (s_val + s_idx) + (d + 1) * 4 + 4 * B * (m + 4 * d) + 4 * d
 
 
@@ -122,26 +130,22 @@ def cpu_baseline(pr, n_iters: int):
                        "%.1f s wall" % (cores, n_iters, dt))
 
 
-def serve_leg(ap, synth, ctx, mat128, pr128, n_req: int, rate: float):
-    """Continuous batching: Poisson arrivals of 64x64 (96 x 90, FP32 matrix) and
-    128x128 (the bench matrix) requests, lambda ~ U[0.005, 0.1], omega in
-    {0.3, 0.6, 1.0}, iteration budgets ~ U{50..300}.  Latency = completion -
-    submission, measured by the server."""
-    geom64 = synth.Geometry(64, 96, 90)
-    pr64 = synth.make_problem(geom64, list(range(500, 516)), tc_range=(1e5, 1e7),
-                              rf_range=(0.05, 0.2))
-    mat64 = ap.load_matrix(ctx, pr64.A, geom64, "f32")
-    rng = np.random.default_rng(2024)
+def serve_leg(ap, ctx, mats, n_req: int, rate: float, seed: int):
+    """Continuous batching: Poisson arrivals of requests whose sizes are uniform over the
+    loaded geometries, total counts log-uniform in [1e5, 1e7] (the problems' own sinograms),
+    lambda ~ U[0.005, 0.1], omega in {0.3, 0.6, 1.0}, iteration budgets ~ U{50..300}.
+    Latency = completion - submission, measured by the server."""
+    rng = np.random.default_rng(seed)
     reqs = []
-    for i in range(n_req):
-        small = rng.random() < 0.5
-        pr, mat = (pr64, mat64) if small else (pr128, mat128)
+    for _ in range(n_req):
+        name = sorted(mats)[int(rng.integers(0, len(mats)))]
+        pr, mat = mats[name]
         b = int(rng.integers(0, len(pr.seeds)))
         p = ap.make_params(lam=float(rng.uniform(0.005, 0.1)), eps=1e-3,
                            omega=float(rng.choice([0.3, 0.6, 1.0])),
                            iterations=int(rng.integers(50, 301)))
         reqs.append((pr, mat, b, p, float(rng.exponential(1.0 / rate))))
-    srv = ap.appga_server_start(ctx, 8 << 30, 64)
+    srv = ap.appga_server_start(ctx, 16 << 30, 64)
     tickets = []
     t0 = time.perf_counter()
     t_next = t0
@@ -152,20 +156,50 @@ def serve_leg(ap, synth, ctx, mat128, pr128, n_req: int, rate: float):
         tickets.append((ap.appga_submit(srv, mat, pr.g[b], pr.gamma[b], p), pr.geom.d, p.iterations))
     lat, iters = [], 0
     for t, d, k in tickets:
-        _, st = ap.appga_wait(srv, t, d, 120000)
+        _, st = ap.appga_wait(srv, t, d, 300000)
         lat.append(st["seconds"])
         iters += k
     dt = time.perf_counter() - t0
     ap.appga_server_stop(srv)
-    ap.appga_free_system_matrix(ctx, mat64)
     lat = np.asarray(lat) * 1e3
     return dict(requests=n_req, offered_rate=rate, throughput_req_s=round(n_req / dt, 1),
                 solve_iterations_per_s=round(iters / dt, 1),
                 p50_ms=round(float(np.percentile(lat, 50)), 3),
                 p99_ms=round(float(np.percentile(lat, 99)), 3),
-                mean_iterations=round(iters / n_req, 1),
-                mix="50% 64x64 (96x90, FP32 matrix) / 50% 128x128 (200x168, bench matrix), "
-                    "lambda U[0.005,0.1], omega {0.3,0.6,1.0}, iterations U{50..300}")
+                mean_iterations=round(iters / n_req, 1))
+
+
+def projector_leg(ap, torch, ctx, pr, mat, steps: int):
+    """Single-solve projectors (B = 1) on the 256 x 256 / 256 bins x 252 angles geometry with
+    an FP32 matrix: the matrix-streaming regime (19.7 M entries in A and in its transpose,
+    FP32 values + uint16 indices, about 118 MB per operator)."""
+    geom = pr.geom
+    g1 = torch.as_tensor(pr.g[0]).cuda()
+    gm1 = torch.as_tensor(pr.gamma[0]).cuda()
+    p = [ap.make_params(lam=0.01, eps=1e-3, omega=1.0, iterations=1000)]
+    s = ap.appga_solve_begin(ctx, mat, g1, gm1, p, None, torch.cuda.current_stream().cuda_stream)
+    for _ in range(5):
+        ap.appga_solve_step(s, 1)
+    torch.cuda.synchronize()
+    ap.appga_set_kernel_timing(ctx, True)
+    for _ in range(steps):
+        ap.appga_solve_step(s, 1)
+    torch.cuda.synchronize()
+    times = ap.appga_kernel_times(ctx)
+    ap.appga_set_kernel_timing(ctx, False)
+    ap.appga_solve_end(s, torch.empty((1, geom.d), dtype=torch.float32, device="cuda"), 1)
+    nnz, m, d = pr.A.nnz, geom.m, geom.d
+    out = {}
+    for name, kind in (("forward_single", "forward"), ("step_single", "step")):
+        t = times.get(name)
+        if not t or t["count"] == 0:
+            continue
+        avg_ms = t["total_ms"] / t["count"]
+        nb = kernel_bytes(kind, nnz, m, d, 1, 4, 2)
+        gbs = nb / (avg_ms * 1e-3) / 1e9
+        out[name] = dict(avg_us=round(1e3 * avg_ms, 2), bytes=nb, gbs=round(gbs, 1),
+                         frac=round(gbs / HBM_PEAK_GBS, 4))
+    return out
 
 
 def main():
@@ -234,7 +268,9 @@ def main():
     s_val = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}[args.storage]
     s_idx = 2 if max(m, d) <= 65536 else 4
     kernels = {}
-    for name, kind in (("forward_batch", "forward"), ("step_batch", "step")):
+    tiles = "back_tiles" in times
+    for name, kind in (("forward_batch", "forward"), ("back_tiles", "back"),
+                       ("step_batch", "update" if tiles else "step")):
         t = times.get(name)
         if not t or t["count"] == 0:
             continue
@@ -269,10 +305,38 @@ def main():
                      ms_per_iter=round(1e3 * dt1 / args.plain_steps, 4),
                      path="single-solve FP32 matrix, the 64 solves one after another")
 
+    # ------------------------------------ 256^2 geometry: projectors, serving ---
+    projector = None
+    pr256 = mat256 = None
+    need256 = not args.no_projector or (args.serve_requests > 0 and not args.profile)
+    if need256:
+        log("building the 256^2 / 256 x 252 geometry")
+        pr256 = synth.make_problem(synth.Geometry(256, 256, 252), list(range(3000, 3008)),
+                                   tc_range=(1e5, 1e7), rf_range=(0.05, 0.2))
+        mat256 = ap.load_matrix(ctx, pr256.A, pr256.geom, "f32")
+    if not args.no_projector:
+        log("single-solve projector leg (256^2, FP32 matrix)")
+        projector = projector_leg(ap, torch, ctx, pr256, mat256, max(20, min(args.steps, 100)))
+
     serving = None
     if args.serve_requests > 0 and not args.profile:
-        log("serving leg: %d requests at %.0f/s" % (args.serve_requests, args.serve_rate))
-        serving = serve_leg(ap, synth, ctx, mat, pr, args.serve_requests, args.serve_rate)
+        geom64 = synth.Geometry(64, 96, 90)
+        pr64 = synth.make_problem(geom64, list(range(500, 516)), tc_range=(1e5, 1e7),
+                                  rf_range=(0.05, 0.2))
+        mat64 = ap.load_matrix(ctx, pr64.A, geom64, "f32")
+        mats = {"064": (pr64, mat64), "128": (pr, mat), "256": (pr256, mat256)}
+        serving = []
+        for i, rate in enumerate(args.serve_rate):
+            log("serving leg: %d requests at %.0f/s" % (args.serve_requests, rate))
+            serving.append(serve_leg(ap, ctx, mats, args.serve_requests, rate, 2024 + i))
+        ap.appga_free_system_matrix(ctx, mat64)
+        serving = dict(
+            mix="sizes uniform over 64x64 (96x90, FP32 matrix), 128x128 (200x168, the bench "
+                "matrix) and 256x256 (256x252, FP32 matrix); lambda U[0.005,0.1], omega "
+                "{0.3,0.6,1.0}, iterations U{50..300}, Poisson arrivals",
+            runs=serving)
+    if mat256 is not None:
+        ap.appga_free_system_matrix(ctx, mat256)
 
     cpu = None
     if not args.no_cpu_baseline and not args.profile:
@@ -306,6 +370,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serving,
+        "projector_single_256": projector,
         "matrix_bytes": info,
         "objective_lane0": stats[0]["objective"],
     }

@@ -225,8 +225,9 @@ appga_status appga_kernel_times(appga_ctx *ctx, int32_t cap, char *names_out, in
  * eq. GNtheta from each request's own iteration counter).
  *
  * One loop thread owns all device work.  Per loaded system matrix it keeps a
- * pool of 64 lanes in device memory (data, background, f, two f~ buffers and
- * the ratio residual per lane: 4*64*(3m + 3d) bytes plus under 64 KiB) and
+ * pool of 64 lanes in device memory (data, background, f, two f~ buffers, the
+ * ratio residual and the back projection per lane; appga_server_footprint
+ * gives its size) and
  * advances every occupied lane of a pool by one iteration per step, replayed
  * from captured hipGraphs on the pool's own stream.  A request is admitted as
  * soon as its pool has a free lane among the first slots_per_matrix (1..64)
@@ -243,6 +244,9 @@ typedef struct {
     int32_t reserved;
 } appga_server_cfg;
 
+/* Device bytes of one 64-lane pool of `mat` (what admission charges against
+ * hbm_budget_bytes).  APPGA_E_INVALID_ARG for NULL arguments. */
+appga_status appga_server_footprint(const appga_matrix *mat, int64_t *bytes);
 /* Starts the loop thread.  APPGA_E_INVALID_ARG for NULL arguments or a
  * non-positive budget or slot count. */
 appga_status appga_server_start(appga_ctx *ctx, const appga_server_cfg *cfg, appga_server **out);

@@ -417,13 +417,18 @@ double orc_theta(int k, double a, double b, double omega)
  * f_hist (nullable, (K+1)*d entries): f^1, ..., f^{K+1}.
  * fixed_p: the diagonal of P in FIXED mode (d entries, or NULL for the
  * scalar fixed_p_scalar in every pixel).
+ * round_f32: a diagnostic, not the method.  When nonzero, the quantities an
+ * FP32 implementation stores between its steps -- f~^k, A f~^k, e, grad F,
+ * grad R and f^{k+1} -- are rounded to the nearest FP32 value each iteration, so that
+ * comparing the run with the exact one measures how much the problem
+ * amplifies FP32-size perturbations injected at every iteration.
  */
 int orc_appga(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, const double *val,
               int n_angles, const double *g, const double *gamma, double lambda1, double lambda2,
               double eps, double omega, double a, double b, double beta, int iterations,
               int momentum, int precond, int precond_freeze_iter, const double *fixed_p,
               double fixed_p_scalar, const double *f_init, double *f_out, double *obj_hist,
-              double *re_hist, double *f_hist, int64_t *clamps)
+              double *re_hist, double *f_hist, int64_t *clamps, int round_f32)
 {
     if (n <= 0 || m < 0 || iterations < 0 || !row_ptr || !g || !gamma || !f_out)
         return ORC_E_ARG;
@@ -459,12 +464,23 @@ int orc_appga(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, cons
         double theta = momentum == ORC_MOMENTUM_NONE ? 0.0 : orc_theta(k, a, b, omega);
         for (size_t j = 0; j < d; ++j)
             ft[j] = f[j] + theta * (f[j] - fprev[j]);
+        if (round_f32)
+            for (size_t j = 0; j < d; ++j) ft[j] = (double)(float)ft[j];
         /* grad F at the extrapolated point */
         orc_forward(m, row_ptr, col, val, ft, y);
+        if (round_f32)
+            for (int64_t i = 0; i < m; ++i) y[i] = (double)(float)y[i];
         orc_ratio(m, y, g, gamma, e, &nclamp);
+        if (round_f32)
+            for (int64_t i = 0; i < m; ++i) e[i] = (double)(float)e[i];
         orc_back(m, (int64_t)d, row_ptr, col, val, e, gF);
         /* grad of the smoothed regulariser at the extrapolated point */
         st = orc_grad_reg(n, lambda1, lambda2, eps, ft, gR);
+        if (round_f32)
+            for (size_t j = 0; j < d; ++j) {
+                gF[j] = (double)(float)gF[j];
+                gR[j] = (double)(float)gR[j];
+            }
         /* diagonal preconditioner */
         if (precond == ORC_PRECOND_FIXED) {
             for (size_t j = 0; j < d; ++j)
@@ -477,6 +493,7 @@ int orc_appga(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, cons
         for (size_t j = 0; j < d; ++j) {
             double z = ft[j] - p[j] * (gF[j] + gR[j]);
             fn[j] = z > 0.0 ? z : 0.0;
+            if (round_f32) fn[j] = (double)(float)fn[j];
         }
         if (re_hist) {
             double dn = 0.0, nn = 0.0;

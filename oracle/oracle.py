@@ -77,7 +77,7 @@ def _declare(lib):
         "orc_init_image": (I32, [I32, I64, I32, P, P, P]),
         "orc_theta": (D, [I32, D, D, D]),
         "orc_appga": (I32, [I32, I64, P, P, P, I32, P, P, D, D, D, D, D, D, D, I32, I32, I32, I32,
-                            P, D, P, P, P, P, P, P]),
+                            P, D, P, P, P, P, P, P, I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -207,11 +207,14 @@ def theta(k, a=0.125, b=1.0, omega=1.0) -> float:
 
 def appga(A, n, n_angles, g, gamma, lam1, lam2, eps, omega, iterations, a=0.125, b=1.0, beta=1.0,
           momentum=MOMENTUM_GN, precond=PRECOND_EM, precond_freeze_iter=0, fixed_p=None,
-          fixed_p_scalar=0.0, f_init=None, history=False, iterates=False):
+          fixed_p_scalar=0.0, f_init=None, history=False, iterates=False, round_f32=False):
     """Run APPGA in FP64.
 
     Returns dict(f=f^{K+1}, obj=[Phi(f^1..f^{K+1})] or None, re=[RE(2..K+1)] or None,
     iterates=(K+1, d) array f^1..f^{K+1} or None, clamps=number of floored bins).
+    round_f32 is a diagnostic (not the method): f~, A f~, e, grad F, grad R and f are
+    rounded to FP32 every iteration, to measure how much a problem amplifies
+    FP32-size perturbations (its sensitivity floor).
     """
     rp, col, val = _csr(A)
     g, gamma = _f64(g), _f64(gamma)
@@ -225,6 +228,6 @@ def appga(A, n, n_angles, g, gamma, lam1, lam2, eps, omega, iterations, a=0.125,
     st = load().orc_appga(n, A.n_rows, _ptr(rp), _ptr(col), _ptr(val), n_angles, _ptr(g),
                           _ptr(gamma), lam1, lam2, eps, omega, a, b, beta, iterations, momentum,
                           precond, precond_freeze_iter, _ptr(fp), fixed_p_scalar, _ptr(fi),
-                          _ptr(f_out), _ptr(obj), _ptr(re), _ptr(fh), _ptr(cl))
+                          _ptr(f_out), _ptr(obj), _ptr(re), _ptr(fh), _ptr(cl), int(bool(round_f32)))
     _check(st, "appga")
     return dict(f=f_out, obj=obj, re=re, iterates=fh, clamps=int(cl[0]))

@@ -93,6 +93,7 @@ _SIGS = {
     "appga_op_step": [P, P, I32, P, P, P, P, P, P, P, P, P, P, P],
     "appga_set_kernel_timing": [P, I32],
     "appga_kernel_times": [P, I32, P, I32, P, P, C.POINTER(I32)],
+    "appga_server_footprint": [P, C.POINTER(I64)],
     "appga_server_start": [P, C.POINTER(appga_server_cfg), PP],
     "appga_submit": [P, P, P, P, C.POINTER(appga_params), C.POINTER(U64)],
     "appga_wait": [P, U64, P, C.POINTER(appga_stats), I32],
@@ -342,6 +343,12 @@ def appga_kernel_times(ctx) -> Dict[str, dict]:
 
 
 # ---------------------------------------------------------------- serving ---
+
+def appga_server_footprint(mat) -> int:
+    b = I64()
+    _call("appga_server_footprint", mat, C.byref(b))
+    return b.value
+
 
 def appga_server_start(ctx, hbm_budget_bytes: int, slots_per_matrix: int) -> int:
     cfg = appga_server_cfg(hbm_budget_bytes, slots_per_matrix, 0)

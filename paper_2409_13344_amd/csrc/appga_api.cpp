@@ -18,6 +18,7 @@
 
 #include "appga_internal.h"
 #include "appga_impl.h"
+#include "back_tiles.h"
 
 using namespace appga;
 
@@ -390,6 +391,29 @@ appga_status to_device(const HostPacked &hp, int64_t nrows, int64_t ncols, int64
     return APPGA_OK;
 }
 
+appga_status back_tiles_to_device(const HostBackTiles &h, DevBackTiles &d) {
+    d = DevBackTiles();
+    d.tiles_x = h.tiles_x;
+    d.n_groups = h.n_groups;
+    d.group_angles = h.group_angles;
+    d.n_entries = static_cast<int64_t>(h.word.size());
+    d.n_rays = static_cast<int64_t>(h.rays.size());
+    ST_TRY(upload(h.rp, reinterpret_cast<void **>(&d.rp), d.bytes));
+    ST_TRY(upload(h.word, reinterpret_cast<void **>(&d.word), d.bytes));
+    ST_TRY(upload(h.ray_off, reinterpret_cast<void **>(&d.ray_off), d.bytes));
+    ST_TRY(upload(h.rays, reinterpret_cast<void **>(&d.rays), d.bytes));
+    d.valid = 1;
+    return APPGA_OK;
+}
+
+void free_back_tiles(DevBackTiles &d) {
+    hipFree(d.rp);
+    hipFree(d.word);
+    hipFree(d.ray_off);
+    hipFree(d.rays);
+    d = DevBackTiles();
+}
+
 void free_csr(DevCsr &dc) {
     hipFree(dc.row_ptr);
     hipFree(dc.col);
@@ -520,6 +544,23 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
         if (st == APPGA_OK) st = to_device(ha, m, d, nnz, vtype, mat->A);
         if (st == APPGA_OK) st = to_device(ht, d, m, nnz, vtype, mat->AT);
     }
+    if (st == APPGA_OK && env_int("APPGA_BACK_TILES", 0)) {
+        // value code of each transpose entry as the stored transpose holds it
+        std::vector<uint32_t> tcode(vtype == VT_F32 ? 0 : nnz);
+        std::vector<float> tv32(vtype == VT_F32 ? nnz : 0);
+        for (int64_t k = 0; k < nnz; ++k) {
+            switch (vtype) {
+                case VT_F32: tv32[k] = static_cast<float>(tval[k]); break;
+                case VT_BF16: tcode[k] = f32_to_bf16(static_cast<float>(tval[k])); break;
+                case VT_F16: tcode[k] = f32_to_f16(static_cast<float>(tval[k])); break;
+                default: tcode[k] = tcodes[k]; break;
+            }
+        }
+        HostBackTiles hb;
+        if (build_back_tiles(geom->n, geom->n_angles, geom->n_bins, trp.data(), tcol.data(), tcode.data(),
+                             tv32.data(), vtype == VT_F32, hb))
+            st = back_tiles_to_device(hb, mat->bt);
+    }
     if (st == APPGA_OK) {
         // Lambda = A^T 1 of the stored (dequantised) values, zeros -> 1 (eq. EM)
         std::vector<double> lam(d, 0.0);
@@ -532,6 +573,7 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
     if (st != APPGA_OK) {
         free_csr(mat->A);
         free_csr(mat->AT);
+        free_back_tiles(mat->bt);
         hipFree(mat->lam);
         delete mat;
         return st;
@@ -543,6 +585,10 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
     const int tx = (geom->n + 3) / 4;
     const bool remap_ok = tx % 4 == 0;
     mat->xcd_remap = (remap_ok && env_int("APPGA_XCD_REMAP", 1)) ? 1 : 0;
+    mat->bt_remap = (mat->bt.valid && mat->bt.tiles_x % 4 == 0 && env_int("APPGA_XCD_REMAP", 1)) ? 1 : 0;
+    mat->bt_split = mat->bt.valid ? std::max(1, std::min(mat->bt.n_groups,
+                                                         env_int("APPGA_BACK_SPLIT", back_tiles_split(mat->bt))))
+                                  : 1;
     *out = mat;
     return APPGA_OK;
 }
@@ -556,6 +602,7 @@ extern "C" appga_status appga_free_system_matrix(appga_ctx *ctx, appga_matrix *m
     hipStreamSynchronize(ctx->stream);
     free_csr(mat->A);
     free_csr(mat->AT);
+    free_back_tiles(mat->bt);
     hipFree(mat->lam);
     delete mat;
     return APPGA_OK;
@@ -657,6 +704,8 @@ static appga_status sess_alloc(appga_solve *s) {
     const size_t o_ft1 = take(sizeof(float) * d * Bp);
     const size_t o_e = take(sizeof(float) * m * Bp);
     const size_t o_pb = s->need_pbuf ? take(sizeof(float) * d * Bp) : 0;
+    const bool tiles = B > 1 && s->mat->bt.valid;
+    const size_t o_gf = tiles ? take(sizeof(float) * d * Bp * s->mat->bt_split) : 0;
     const size_t o_lp = take(sizeof(LaneParams) * Bp);
     s->theta_cap = 1024;
     const size_t o_th = take(sizeof(float) * (s->theta_cap + 2) * Bp);
@@ -674,6 +723,7 @@ static appga_status sess_alloc(appga_solve *s) {
     s->ft[1] = reinterpret_cast<float *>(base + o_ft1);
     s->e = reinterpret_cast<float *>(base + o_e);
     s->pbuf = s->need_pbuf ? reinterpret_cast<float *>(base + o_pb) : nullptr;
+    s->gf = tiles ? reinterpret_cast<float *>(base + o_gf) : nullptr;
     s->lp = reinterpret_cast<LaneParams *>(base + o_lp);
     s->theta = reinterpret_cast<float *>(base + o_th);
     s->part = reinterpret_cast<double *>(base + o_part);
@@ -910,6 +960,14 @@ appga_status sess_step(appga_solve *s, int n_iters) {
         sa.re_part = (it == n_iters - 1) ? s->part : nullptr;
         sa.tiles_x = (mat->geom.n + 3) / 4;
         sa.xcd_remap = mat->xcd_remap;
+        if (s->gf) {
+            HIP_TRY(timed_launch(s->ctx, "back_tiles", s->st, [&] {
+                return launch_back_tiles(mat->bt, mat->AT.vtype, mat->geom.n, mat->A.n_rows, s->Bp,
+                                         mat->bt_remap, mat->bt_split, s->e, s->gf, s->st);
+            }));
+            sa.gf_in = s->gf;
+            sa.gf_split = mat->bt_split;
+        }
         HIP_TRY(timed_launch(s->ctx, B == 1 ? "step_single" : "step_batch", s->st,
                              [&] { return launch_step(mat->AT, sa, mat->group_back, s->st); }));
         s->cur ^= 1;
@@ -1190,11 +1248,13 @@ appga_status op_step_impl(appga_ctx *ctx, const appga_matrix *mat, int n, int B,
     const int64_t m = mat ? mat->A.n_rows : 0;
     const int Bp = pad_lanes(B);
     OpBufs ob;
-    const size_t nfl = static_cast<size_t>(d) * Bp * 4 + static_cast<size_t>(m) * Bp + Bp;
+    const int split = mat ? mat->bt_split : 1;
+    const size_t nfl = static_cast<size_t>(d) * Bp * (4 + split) + static_cast<size_t>(m) * Bp + Bp;
     const size_t lp_off = (sizeof(float) * nfl + 255) / 256 * 256;
     HIP_TRY(hipMalloc(&ob.mem, lp_off + sizeof(LaneParams) * Bp));
     float *e = static_cast<float *>(ob.mem);
-    float *ft = e + m * Bp, *f = ft + d * Bp, *ftn = f + d * Bp, *out = ftn + d * Bp, *th = out + d * Bp;
+    float *ft = e + m * Bp, *f = ft + d * Bp, *ftn = f + d * Bp, *out = ftn + d * Bp, *gf = out + d * Bp,
+          *th = gf + d * Bp * split;
     LaneParams *lp = reinterpret_cast<LaneParams *>(static_cast<char *>(ob.mem) + lp_off);
     if (d_e) ST_TRY(to_internal(d_e, e, B, m, st));
     if (d_e && scale_rows && mat && mat->A.row_scale)
@@ -1246,6 +1306,15 @@ appga_status op_step_impl(appga_ctx *ctx, const appga_matrix *mat, int n, int B,
     sa.xcd_remap = mat ? mat->xcd_remap : 0;
     const int group = mat ? mat->group_back : 16;
     const char *name = out_mode == SO_REG ? "op_grad_reg" : (out_mode == SO_BACK ? "op_back" : "op_step");
+    const bool tiles = mat && B > 1 && mat->bt.valid && out_mode != SO_REG;
+    if (tiles) {
+        HIP_TRY(timed_launch(ctx, "op_back_tiles", st, [&] {
+            return launch_back_tiles(mat->bt, AT.vtype, n, static_cast<int>(m), Bp, mat->bt_remap, split, e,
+                                     gf, st);
+        }));
+        sa.gf_in = gf;
+        sa.gf_split = split;
+    }
     HIP_TRY(timed_launch(ctx, name, st, [&] { return launch_step(AT, sa, group, st); }));
     if (out_mode == SO_STEP) {
         ST_TRY(from_internal(f, d_f, B, d, st));

@@ -32,12 +32,15 @@ struct appga_matrix {
     int64_t nnz = 0;
     int storage = 0;
     appga::DevCsr A, AT;
+    appga::DevBackTiles bt;            // B > 1 back projection over pixel tiles (bt.valid = 0: none)
     float *lam = nullptr;              // Lambda (d), device
     std::vector<double> deq;           // dequantised values in the caller's CSR order
     std::vector<int64_t> user_row_ptr; // caller's CSR structure (for reports)
     std::vector<int32_t> user_col;
     int group_fwd = 16, group_back = 16;
     int xcd_remap = 0;
+    int bt_remap = 0;                  // XCD remap of the 8 x 8 tile grid
+    int bt_split = 1;                  // workgroups (partial sums) per tile of the back projection
     int fwd_wgs = 2048;                // batched forward: workgroups of the row-strided grid
     mutable std::atomic<int> inflight{0};
     uint64_t serial = 0;               // unique per load (servers key their pools by it)
@@ -54,6 +57,7 @@ struct appga_solve {
     void *arena = nullptr;
     float *g = nullptr, *gamma = nullptr, *gamma_lane = nullptr, *f = nullptr, *ft[2] = {nullptr, nullptr},
           *e = nullptr, *pbuf = nullptr, *theta = nullptr;
+    float *gf = nullptr;   // A^T e from the tile kernel (B > 1 with tiles), else null
     appga::LaneParams *lp = nullptr;
     double *part = nullptr, *red = nullptr, *tmc = nullptr;
     unsigned long long *clamps = nullptr;

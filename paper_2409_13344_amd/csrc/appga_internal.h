@@ -36,6 +36,53 @@ struct DevCsr {
     int64_t bytes = 0;           // stored bytes (values + indices + row_ptr + scales)
 };
 
+// Back projection over pixel tiles for B > 1 (built from the transpose at load
+// time).  The image is cut into kBackTile x kBackTile tiles; the angles into
+// groups of `group_angles` consecutive angles (rays i with
+// i / (n_bins * group_angles) == g).  For tile t and group g, the distinct
+// rays that cross the tile, ascending, are the slots of the residual window
+// staged in LDS: rays[ray_off[t*G + g] + s] is the ray in slot s (at most
+// kBackSlots slots).  The entries of tile-local pixel p (row-major within the
+// tile) in group g are entries [rp[(t*G + g)*64 + p], rp[... + 1]) (at most 64),
+// in ray order: word = slot*256 | code << 16 for 16- and 8-bit values (the
+// stored value code); for FP32 values each entry is two words, slot*256 and
+// the value's bits, and the offsets count words.  The lists of the pixel pair
+// (2i, 2i+1) are padded to one common multiple of 4 entries with zero-valued
+// entries whose slot is kBackSlots (a record of zeros the kernel keeps in
+// LDS).  Device pointers.
+constexpr int kBackTile = 8;
+constexpr int kBackSlots = 96;       // records per window (slot kBackSlots is the zero record)
+constexpr int kBackMaxGroups = 48;
+constexpr int kBackMaxWords = 2048;  // entries of one tile in one group (padded)
+
+struct DevBackTiles {
+    int valid = 0;
+    int tiles_x = 0, n_groups = 0, group_angles = 0;
+    uint32_t *rp = nullptr;
+    uint32_t *word = nullptr;
+    uint32_t *ray_off = nullptr;
+    uint32_t *rays = nullptr;
+    int64_t n_entries = 0, n_rays = 0;
+    int64_t bytes = 0;
+};
+
+struct BackTileArgs {
+    const uint32_t *rp;
+    const uint32_t *word;
+    const uint32_t *ray_off;
+    const uint32_t *rays;
+    uint32_t n_entries;     // length of word
+    uint32_t n_rays;        // length of rays
+    int n;                  // image side
+    int tiles_x;            // tiles per image row
+    int n_groups;
+    int m;                  // rays (length of e per solve)
+    int xcd_remap;
+    int split;              // workgroups per tile; workgroup s sums groups [s G / split, (s+1) G / split)
+    const float *e;         // [m] lane layout, chunk blockIdx.y
+    float *out;             // [split][d] lane layout: the partial sums of A^T e
+};
+
 // Per-solve (per batch lane) parameters, FP32 copies of the FP64 host values.
 struct LaneParams {
     float lambda1, lambda2, eps, beta, fixed_p, pad0, pad1, pad2;
@@ -103,6 +150,8 @@ struct StepArgs {
     const LaneParams *lp;    // [B]
     const float *theta_next; // [B] theta_{k+1}
     float *pbuf;             // [d][B] frozen preconditioner (or null)
+    const float *gf_in;      // B > 1: A^T e from the tile kernel as gf_split partial sums (or null: gather here)
+    int gf_split;            // number of partial sums in gf_in ([gf_split][d][Bp], added in order)
     int pmode;               // PMode
     int out_mode;            // StepOut
     float *out;              // [d][B] for SO_BACK / SO_REG
@@ -112,6 +161,13 @@ struct StepArgs {
 };
 
 // Serving helpers (kernels.hip).
+// B > 1 back projection out = A^T e over the tiles (lane layout, Bp / 64 chunks).
+hipError_t launch_back_tiles(const DevBackTiles &bt, int vtype, int n, int m, int Bp, int xcd_remap,
+                             int split, const float *e, float *out, hipStream_t st);
+// Workgroups per tile for the back projection of an n x n image (enough
+// workgroups to put two on every CU).
+int back_tiles_split(const DevBackTiles &bt);
+
 // Serving: advances the 64 per-lane iteration counters k by one and writes
 // theta_{k+1} (eq. GNtheta, FP64) per lane; mom holds {a, b, omega, momentum_none}.
 hipError_t launch_lane_theta(int *lane_k, const double *mom, float *theta, hipStream_t st);

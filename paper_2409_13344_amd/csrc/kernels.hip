@@ -514,7 +514,17 @@ __global__ __launch_bounds__(1024, 8) void k_step_batch(StepArgs a) {
     const size_t vbase = static_cast<size_t>(chunk) * d * 64 + lane;
 
     float gF = 0.0f;
-    if (a.out_mode != SO_REG && in) {
+    // values of the update, loaded before the halo so their latency overlaps it
+    const bool upd = in && a.out_mode == SO_STEP;
+    const float fk = upd ? a.f[vbase + static_cast<size_t>(r * N + c) * 64] : 0.0f;
+    const float lamj = upd ? a.lam[r * N + c] : 1.0f;
+    if (a.gf_in) {
+        if (in) {
+            const size_t o = vbase + static_cast<size_t>(r * N + c) * 64;
+            const size_t stride = static_cast<size_t>(a.Bp) * d;
+            for (int q = 0; q < a.gf_split; ++q) gF += a.gf_in[q * stride + o];
+        }
+    } else if (a.out_mode != SO_REG && in) {
         const int j = r * N + c;
         const auto er = make_rsrc(reinterpret_cast<const char *>(a.e) + static_cast<size_t>(chunk) * a.m * 256,
                                   256u * static_cast<uint32_t>(a.m));
@@ -554,8 +564,7 @@ __global__ __launch_bounds__(1024, 8) void k_step_batch(StepArgs a) {
                 a.out[o] = gR;
             } else {
                 const float th = a.theta_next[b];
-                const float fk = a.f[o];
-                const float P = precond(a.pmode, fk, a.lam[r * N + c], lp, a.pbuf, o);
+                const float P = precond(a.pmode, fk, lamj, lp, a.pbuf, o);
                 const float z = ftc - P * (gF + gR);
                 const float fn = z > 0.0f ? z : 0.0f;
                 a.f[o] = fn;
@@ -583,6 +592,244 @@ __global__ __launch_bounds__(1024, 8) void k_step_batch(StepArgs a) {
             a.re_part[po] = s0;
             a.re_part[po + 1] = s1;
         }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Back projection grad F = A^T e for B > 1 over 8 x 8 pixel tiles (Section 2.2).
+//
+// Every nonzero of A^T needs the 256-byte lane record of one ray's residual.
+// Gathering those records one by one from L2 is what bounds a row-by-row
+// kernel; here the records a tile needs are staged in LDS and reused.  For a
+// group of consecutive angles only a few rays per angle cross an 8 x 8 tile
+// (about 8 sqrt 2 + 2), so the tile's window for one group is at most
+// kBackSlots records; each is read from L2 once per tile and then serves every
+// entry of the tile's pixels in that group (about 8 on average).  Windows are
+// double buffered: the next group's records are in flight while the current
+// group is summed.  A tile's angle groups are split between `split`
+// workgroups (each writes its own partial sum), so that two workgroups share
+// a CU and one sums while the other waits for its window.  Workgroup = 8
+// waves, lanes = the 64 solves of chunk blockIdx.y; wave w sums the 8 pixels
+// of tile row w; per entry one v_readlane of the packed word (LDS byte offset
+// | value code), one LDS read with the lane as offset and one FMA.  Entries
+// are in the transpose's ray order.
+// ------------------------------------------------------------------------
+
+template <int VT>
+__device__ __forceinline__ float tile_val(uint32_t word, uint32_t v32) {
+    if constexpr (VT == VT_F32) return __uint_as_float(v32);
+    else if constexpr (VT == VT_BF16) return __uint_as_float(word & 0xFFFF0000u);
+    else if constexpr (VT == VT_F16) return f16_to_f32(word >> 16);
+    else return fp8_to_f32((word >> 16) & 0xFFu);
+}
+
+constexpr int kBackThreads = 512;
+constexpr int kBackPix = 8;         // pixels per wave (one tile row)
+
+// LDS of the back projection: one array at LDS address 0 (the kernel's only
+// LDS object, 32 KB aligned) so that the second window starts at 32 KB and a
+// record's byte address is (slot * 256) | (window << 15) | (lane << 2): one
+// v_and_or per entry.  Between and after the windows: the ray ids of the next
+// two windows, the tile's word offsets, and two buffers of staged words.
+constexpr uint32_t kWinBytes = (kBackSlots + 1) * 256;
+constexpr uint32_t kWin1 = 32768;
+constexpr uint32_t kIdsOff = kWinBytes;                                  // u32 [2][kBackSlots]
+constexpr uint32_t kWbOff = kIdsOff + 2 * kBackSlots * 4;                // u32 [kBackMaxGroups + 1]
+constexpr uint32_t kRelOff = kWbOff + (kBackMaxGroups + 1) * 4;          // u16 [kBackMaxGroups][65]
+constexpr uint32_t kWordsOff = kWin1 + kWinBytes;                        // u32 [2][kBackMaxWords]
+constexpr uint32_t kBackLds = kWordsOff + 2 * kBackMaxWords * 4;
+static_assert(kRelOff + kBackMaxGroups * 65 * 2 <= kWin1, "back projection LDS layout");
+static_assert(kBackSlots * 256 <= 0x7F00, "slot offsets must fit bits 8..14");
+static_assert(kBackMaxWords == 4 * kBackThreads, "one 16-byte word quad per thread");
+
+template <int VT>
+__global__ __launch_bounds__(kBackThreads) void k_back_tiles(BackTileArgs a) {
+    __shared__ __attribute__((aligned(32768))) uint32_t lds[kBackLds / 4];
+    char *const lb = reinterpret_cast<char *>(lds);
+    uint32_t *const ids = reinterpret_cast<uint32_t *>(lb + kIdsOff);
+    uint32_t *const wbase = reinterpret_cast<uint32_t *>(lb + kWbOff);
+    uint16_t *const rel = reinterpret_cast<uint16_t *>(lb + kRelOff);
+    uint32_t *const words = reinterpret_cast<uint32_t *>(lb + kWordsOff);
+    constexpr int kQ = (kBackSlots * 16 + kBackThreads - 1) / kBackThreads;   // window quads per thread
+    constexpr int kR = (kBackMaxGroups * 65 + kBackThreads - 1) / kBackThreads;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int N = a.n;
+    const int tx = a.tiles_x;
+    const int ntiles = tx * tx;
+    const int part = blockIdx.x / ntiles;
+    const int tile = tile_of(blockIdx.x - part * ntiles, tx, tx, a.xcd_remap);
+    const int r0 = (tile / tx) * kBackTile, c0 = (tile % tx) * kBackTile;
+    const int NG = a.n_groups;
+    const int g0 = part * NG / a.split, g1 = (part + 1) * NG / a.split;
+    const int chunk = blockIdx.y;
+    const size_t tg0 = static_cast<size_t>(tile) * NG;
+    // Every global load below is unconditional and range-checked by its buffer
+    // descriptor (out of range reads 0), so the wait counts stay static.
+    const auto er = make_rsrc(reinterpret_cast<const char *>(a.e) + static_cast<size_t>(chunk) * a.m * 256,
+                              256u * static_cast<uint32_t>(a.m));
+    const auto rr = make_rsrc(a.rays, 4u * a.n_rays);
+    const auto wr = make_rsrc(a.word, 4u * a.n_entries);
+    const auto pr = make_rsrc(a.rp + tg0 * 64, 4u * static_cast<uint32_t>(NG * 64 + 1));
+
+    // set-up: zero records, the groups' word offsets (absolute, then relative)
+    if (w == 0) {
+        lds[(kBackSlots * 256) / 4 + lane] = 0u;
+        lds[(kWin1 + kBackSlots * 256) / 4 + lane] = 0u;
+    }
+    if (tid <= NG) wbase[tid] = __builtin_amdgcn_raw_buffer_load_b32(pr, 4u * (64u * tid), 0, 0);
+    {
+        uint32_t v[kR];
+#pragma unroll
+        for (int j = 0; j < kR; ++j) {
+            const uint32_t i = tid + kBackThreads * j, g = i / 65u, p = i % 65u;
+            v[j] = __builtin_amdgcn_raw_buffer_load_b32(pr, 4u * (64u * g + p), 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kR; ++j) {
+            const uint32_t i = tid + kBackThreads * j, g = i / 65u;
+            if (g < static_cast<uint32_t>(NG)) rel[i] = static_cast<uint16_t>(v[j] - wbase[g]);
+        }
+    }
+
+    // ray ids of a group: global -> registers -> LDS, two groups ahead of the sums
+    uint32_t rid = 0u;
+    auto ids_load = [&](int g) {
+        rid = __builtin_amdgcn_raw_buffer_load_b32(rr, 4u * (a.ray_off[tg0 + g] + tid), 0, 0);
+    };
+    auto ids_store = [&](int buf) {
+        if (tid < kBackSlots) ids[buf * kBackSlots + tid] = rid;
+    };
+    // a group's window records (thread tid moves quads tid + kBackThreads j of
+    // 16 per record) and its words (one quad per thread)
+    uint4 stq[kQ], wq;
+    auto stage_load = [&](int g, int buf) {
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) {
+            const uint32_t q = tid + kBackThreads * j, qp = q & 15u;
+            const uint32_t ray = ids[buf * kBackSlots + (q >> 4)];
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(er, ray * 256u + qp * 16u, 0, 0);
+            stq[j] = make_uint4(v[0], v[1], v[2], v[3]);
+        }
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(wr, 4u * (wbase[g] + 4u * tid), 0, 0);
+        wq = make_uint4(v[0], v[1], v[2], v[3]);
+    };
+    auto stage_store = [&](int g, int buf) {
+        const uint32_t S = a.ray_off[tg0 + g + 1] - a.ray_off[tg0 + g];
+        char *const wb = lb + (buf ? kWin1 : 0u);
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) {
+            const uint32_t q = tid + kBackThreads * j, rec = q >> 4, qp = q & 15u;
+            if (rec < S) *reinterpret_cast<uint4 *>(wb + rec * 256 + qp * 16) = stq[j];
+        }
+        if (4u * tid < wbase[g + 1] - wbase[g])
+            *reinterpret_cast<uint4 *>(&words[buf * kBackMaxWords + 4 * tid]) = wq;
+    };
+
+    float acc[kBackPix];
+#pragma unroll
+    for (int p = 0; p < kBackPix; ++p) acc[p] = 0.0f;
+    // sums of group g from window BUF (a compile-time buffer, so that its base
+    // is the LDS read's immediate offset): the words of a pixel pair are read
+    // four entries at a time at one address for the whole wave (an LDS
+    // broadcast); a record's address is (slot * 256) | (lane << 2), assembled by
+    // one v_perm from the word's byte 1 and the lane offset
+    const uint32_t lane4 = static_cast<uint32_t>(lane) << 2;
+    auto compute = [&](int g, auto bufc) {
+        constexpr int BUF = decltype(bufc)::value;
+        const char *const wbase_lds = lb + (BUF ? kWin1 : 0u);
+        const uint32_t *wl = words + BUF * kBackMaxWords;
+        const uint16_t *rg = rel + g * 65 + w * kBackPix;
+        auto xval = [&](uint32_t word) {
+            return *reinterpret_cast<const float *>(wbase_lds + __builtin_amdgcn_perm(word, lane4, 0x0C0C0500u));
+        };
+#pragma unroll
+        for (int p = 0; p < kBackPix; p += 2) {
+            const int s0 = __builtin_amdgcn_readfirstlane(rg[p]);
+            const int s1 = __builtin_amdgcn_readfirstlane(rg[p + 1]);
+            const int n = s1 - s0;       // the pair's lists have equal lengths
+            float u0 = acc[p], u1 = acc[p + 1];
+            if constexpr (VT == VT_F32) {
+                for (int t = 0; t < n; t += 8) {      // (word, value) pairs
+                    const uint4 a0 = *reinterpret_cast<const uint4 *>(wl + s0 + t);
+                    const uint4 a1 = *reinterpret_cast<const uint4 *>(wl + s0 + t + 4);
+                    const uint4 b0 = *reinterpret_cast<const uint4 *>(wl + s1 + t);
+                    const uint4 b1 = *reinterpret_cast<const uint4 *>(wl + s1 + t + 4);
+                    const float xa[4] = {xval(a0.x), xval(a0.z), xval(a1.x), xval(a1.z)};
+                    const float xb[4] = {xval(b0.x), xval(b0.z), xval(b1.x), xval(b1.z)};
+                    u0 = fmaf(__uint_as_float(a0.y), xa[0], u0);
+                    u1 = fmaf(__uint_as_float(b0.y), xb[0], u1);
+                    u0 = fmaf(__uint_as_float(a0.w), xa[1], u0);
+                    u1 = fmaf(__uint_as_float(b0.w), xb[1], u1);
+                    u0 = fmaf(__uint_as_float(a1.y), xa[2], u0);
+                    u1 = fmaf(__uint_as_float(b1.y), xb[2], u1);
+                    u0 = fmaf(__uint_as_float(a1.w), xa[3], u0);
+                    u1 = fmaf(__uint_as_float(b1.w), xb[3], u1);
+                }
+            } else {
+                for (int t = 0; t < n; t += 4) {
+                    const uint4 wa = *reinterpret_cast<const uint4 *>(wl + s0 + t);
+                    const uint4 wb2 = *reinterpret_cast<const uint4 *>(wl + s1 + t);
+                    const float xa[4] = {xval(wa.x), xval(wa.y), xval(wa.z), xval(wa.w)};
+                    const float xb[4] = {xval(wb2.x), xval(wb2.y), xval(wb2.z), xval(wb2.w)};
+                    u0 = fmaf(tile_val<VT>(wa.x, 0u), xa[0], u0);
+                    u1 = fmaf(tile_val<VT>(wb2.x, 0u), xb[0], u1);
+                    u0 = fmaf(tile_val<VT>(wa.y, 0u), xa[1], u0);
+                    u1 = fmaf(tile_val<VT>(wb2.y, 0u), xb[1], u1);
+                    u0 = fmaf(tile_val<VT>(wa.z, 0u), xa[2], u0);
+                    u1 = fmaf(tile_val<VT>(wb2.z, 0u), xb[2], u1);
+                    u0 = fmaf(tile_val<VT>(wa.w, 0u), xa[3], u0);
+                    u1 = fmaf(tile_val<VT>(wb2.w, 0u), xb[3], u1);
+                }
+            }
+            acc[p] = u0;
+            acc[p + 1] = u1;
+        }
+    };
+
+    // Buffers alternate with the group's position in the workgroup's range
+    // (group g0 + i uses buffer i & 1).  Group g is summed while group g + 1's
+    // records and words and group g + 2's ray ids are in flight.
+    auto iter = [&](int g, auto bufc) {
+        constexpr int BUF = decltype(bufc)::value;
+        const bool more = g + 1 < g1;
+        const bool more2 = g + 2 < g1;
+        if (more) {
+            stage_load(g + 1, BUF ^ 1);
+            if (more2) ids_load(g + 2);
+        }
+        compute(g, bufc);
+        if (more) stage_store(g + 1, BUF ^ 1);
+        if (more2) ids_store(BUF);
+        // all loads of this iteration have landed (the buffer stores waited for them)
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __syncthreads();
+    };
+    if (g0 < g1) {
+        ids_load(g0);
+        ids_store(0);
+        if (g0 + 1 < g1) {
+            ids_load(g0 + 1);
+            ids_store(1);
+        }
+        __syncthreads();
+        stage_load(g0, 0);
+        stage_store(g0, 0);
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __syncthreads();
+    }
+    for (int g = g0; g < g1; g += 2) {
+        iter(g, std::integral_constant<int, 0>{});
+        if (g + 1 < g1) iter(g + 1, std::integral_constant<int, 1>{});
+    }
+    const int rr0 = r0 + w;
+    float *out = a.out + (static_cast<size_t>(part) * gridDim.y + chunk) * N * N * 64;
+#pragma unroll
+    for (int p = 0; p < kBackPix; ++p) {
+        const int cc = c0 + p;
+        if (rr0 < N && cc < N) out[(static_cast<size_t>(rr0) * N + cc) * 64 + lane] = acc[p];
     }
 }
 
@@ -971,6 +1218,41 @@ hipError_t launch_scale_rows(float *e, const float *scale, int m, int B, hipStre
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scale_rows, dim3(blocks_for(n)), dim3(256), 0, st, e, scale, m, B,
                        pad_lanes(B));
+    return hipGetLastError();
+}
+
+int back_tiles_split(const DevBackTiles &bt) {
+    const int ntiles = bt.tiles_x * bt.tiles_x;
+    return (ntiles < 512 && bt.n_groups >= 2) ? 2 : 1;
+}
+
+hipError_t launch_back_tiles(const DevBackTiles &bt, int vtype, int n, int m, int Bp, int xcd_remap,
+                             int split, const float *e, float *out, hipStream_t st) {
+    if (!bt.valid || Bp < 64 || Bp % 64 != 0 || split < 1 || split > bt.n_groups) return hipErrorInvalidValue;
+    BackTileArgs a{};
+    a.rp = bt.rp;
+    a.word = bt.word;
+    a.ray_off = bt.ray_off;
+    a.rays = bt.rays;
+    a.n_entries = static_cast<uint32_t>(bt.n_entries);
+    a.n_rays = static_cast<uint32_t>(bt.n_rays);
+    a.n = n;
+    a.tiles_x = bt.tiles_x;
+    a.n_groups = bt.n_groups;
+    a.m = m;
+    a.xcd_remap = xcd_remap;
+    a.split = split;
+    a.e = e;
+    a.out = out;
+    const dim3 grid(static_cast<unsigned>(bt.tiles_x * bt.tiles_x * split), static_cast<unsigned>(Bp / 64));
+    const dim3 blk(kBackThreads);
+    switch (vtype) {
+        case VT_F32: hipLaunchKernelGGL(k_back_tiles<VT_F32>, grid, blk, 0, st, a); break;
+        case VT_BF16: hipLaunchKernelGGL(k_back_tiles<VT_BF16>, grid, blk, 0, st, a); break;
+        case VT_F16: hipLaunchKernelGGL(k_back_tiles<VT_F16>, grid, blk, 0, st, a); break;
+        case VT_FP8: hipLaunchKernelGGL(k_back_tiles<VT_FP8>, grid, blk, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

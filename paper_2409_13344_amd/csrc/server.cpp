@@ -58,6 +58,7 @@ struct Pool {
     void *arena = nullptr;
     int64_t bytes = 0;
     float *g = nullptr, *gamma = nullptr, *f = nullptr, *ft[2] = {nullptr, nullptr}, *e = nullptr;
+    float *gf = nullptr;                              // A^T e of the tile kernel (or null)
     LaneParams *lp = nullptr;
     double *mom = nullptr;
     int *lane_k = nullptr;
@@ -110,7 +111,7 @@ namespace {
 
 // Byte offsets of one pool's buffers inside its arena.
 struct PoolLayout {
-    size_t g, gamma, f, ft0, ft1, e, lp, mom, k, theta, clamps, stage_in, stage_out, total;
+    size_t g, gamma, f, ft0, ft1, e, gf, lp, mom, k, theta, clamps, stage_in, stage_out, total;
 };
 
 PoolLayout pool_layout(const appga_matrix *mat) {
@@ -128,6 +129,7 @@ PoolLayout pool_layout(const appga_matrix *mat) {
     L.ft0 = take(4 * d * kLanes);
     L.ft1 = take(4 * d * kLanes);
     L.e = take(4 * m * kLanes);
+    L.gf = mat->bt.valid ? take(4 * d * kLanes * mat->bt_split) : 0;
     L.lp = take(sizeof(LaneParams) * kLanes);
     L.mom = take(sizeof(double) * 4 * kLanes);
     L.k = take(sizeof(int) * kLanes);
@@ -199,11 +201,16 @@ hipError_t capture_step(Pool *p, int cur, hipGraphExec_t *out) {
     sa.re_part = nullptr;
     sa.tiles_x = (mat->geom.n + 3) / 4;
     sa.xcd_remap = mat->xcd_remap;
+    sa.gf_in = p->gf;
+    sa.gf_split = mat->bt_split;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t e1 = launch_lane_theta(p->lane_k, p->mom, p->theta, p->stream);
     if (e1 == hipSuccess) e1 = launch_forward(mat->A, fa, mat->group_fwd, p->stream);
+    if (e1 == hipSuccess && p->gf)
+        e1 = launch_back_tiles(mat->bt, mat->AT.vtype, mat->geom.n, mat->A.n_rows, kLanes, mat->bt_remap,
+                               mat->bt_split, p->e, p->gf, p->stream);
     hipError_t e2 = e1 == hipSuccess ? launch_step(mat->AT, sa, mat->group_back, p->stream) : e1;
     e = hipStreamEndCapture(p->stream, &graph);
     if (e1 != hipSuccess) return e1;
@@ -234,6 +241,7 @@ appga_status create_pool(appga_server *srv, const appga_matrix *mat, std::unique
     p->ft[0] = reinterpret_cast<float *>(base + L.ft0);
     p->ft[1] = reinterpret_cast<float *>(base + L.ft1);
     p->e = reinterpret_cast<float *>(base + L.e);
+    p->gf = mat->bt.valid ? reinterpret_cast<float *>(base + L.gf) : nullptr;
     p->lp = reinterpret_cast<LaneParams *>(base + L.lp);
     p->mom = reinterpret_cast<double *>(base + L.mom);
     p->lane_k = reinterpret_cast<int *>(base + L.k);
@@ -513,6 +521,13 @@ void run_loop(appga_server *srv) {
 }
 
 }  // namespace
+
+extern "C" appga_status appga_server_footprint(const appga_matrix *mat, int64_t *bytes) {
+    clear_error();
+    if (!mat || !bytes) return fail(APPGA_E_INVALID_ARG, "NULL matrix or output");
+    *bytes = pool_bytes(mat);
+    return APPGA_OK;
+}
 
 extern "C" appga_status appga_server_start(appga_ctx *ctx, const appga_server_cfg *cfg,
                                            appga_server **out) {

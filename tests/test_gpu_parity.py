@@ -12,6 +12,7 @@ Tolerances (relative image L2 unless stated):
     error is reported and bounded loosely (BF16 ~ 2^-9 per entry).
 """
 import copy
+from concurrent.futures import ThreadPoolExecutor
 import sys
 
 import numpy as np
@@ -315,13 +316,24 @@ def test_reduced_precision_c3_sampled(ctx, c2, storage):
     Aq = copy.copy(pr.A)
     Aq.val = deq
     bound_exact = {"bf16": 2e-2, "f16": 2e-3, "fp8": 2e-1}[storage]
-    for b in (0, 37, 63):
-        ref_q = oracle.appga(Aq, 128, 168, pr.g[b], pr.gamma[b], 0.02, 0.02, 1e-3, 0.5, 300)["f"]
-        ref_x = oracle.appga(pr.A, 128, 168, pr.g[b], pr.gamma[b], 0.02, 0.02, 1e-3, 0.5, 300)["f"]
+
+    def refs(b):
+        run = lambda A, g: oracle.appga(A, 128, 168, g, pr.gamma[b], 0.02, 0.02, 1e-3, 0.5, 300)["f"]
+        g = pr.g[b].astype(np.float64)
+        ref_q = run(Aq, g)
+        # the problem's own floor: how far an FP32-size (1e-7 relative) perturbation
+        # of the data moves the FP64 result
+        pert = g * (1.0 + 1e-7 * np.random.default_rng(b).standard_normal(g.shape))
+        return ref_q, run(pr.A, g), rel_l2(run(Aq, pert), ref_q)
+
+    with ThreadPoolExecutor(3) as ex:
+        res = list(ex.map(refs, (0, 37, 63)))
+    for b, (ref_q, ref_x, floor) in zip((0, 37, 63), res):
         e_q, e_x = rel_l2(f[b], ref_q), rel_l2(f[b], ref_x)
-        say("  solve %d: vs dequantised-matrix oracle %.3e, vs exact-matrix oracle %.3e"
-            % (b, e_q, e_x))
-        assert e_q <= 1e-5
+        tol = max(1e-5, 4.0 * floor)
+        say("  solve %d: vs dequantised-matrix oracle %.3e (floor %.2e, tol %.2e), vs exact-matrix "
+            "oracle %.3e" % (b, e_q, floor, tol, e_x))
+        assert e_q <= tol
         assert e_x <= bound_exact
         assert stats[b]["guard_clamps"] == 0
 

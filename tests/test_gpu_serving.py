@@ -135,9 +135,12 @@ def test_served_results_match_solo_and_mix(setup):
 
 def test_budget_admits_one_pool_at_a_time(setup):
     ctx, mats, probs = setup
-    # lane pools: 128^2 about 38.4 MB, 64^2 about 9.8 MB; a 45 MB budget holds one
-    # of them, so the second geometry waits until the first pool drains and is freed
-    srv = ap.appga_server_start(ctx, 45 << 20, 8)
+    # a budget that holds either pool but not both: the second geometry waits
+    # until the first pool drains and is freed
+    big = ap.appga_server_footprint(mats["mid"])
+    small = ap.appga_server_footprint(mats["small"])
+    assert big > small > 0
+    srv = ap.appga_server_start(ctx, big + small // 2, 8)
     try:
         ts = []
         for i in range(6):
