@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -52,6 +53,17 @@ struct Request {
     bool done = false;
 };
 
+// Pinned host staging of one admission: data, background and the lane's
+// small state, copied to the device in stream order; reusable once `ev` has
+// completed.
+struct Stage {
+    float *h = nullptr;      // g (m), gamma (m), then LaneParams, {a, b, omega, none}, k0, clamps
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+constexpr int kStageRing = 8;
+constexpr int kDepth = 16;   // steps in flight per pool
+
 struct Pool {
     const appga_matrix *mat = nullptr;
     hipStream_t stream = nullptr;
@@ -62,25 +74,25 @@ struct Pool {
     LaneParams *lp = nullptr;
     double *mom = nullptr;
     int *lane_k = nullptr;
-    float *theta = nullptr;                           // [64] theta_{k+1}, written by the forward
+    float *theta = nullptr;                           // [64] theta_{k+1}
     unsigned long long *clamps = nullptr;
     float *stage_in = nullptr, *stage_out = nullptr;  // device staging (m floats, d floats)
-    float *h_in = nullptr;                            // pinned host staging (2 m floats)
+    Stage stages[kStageRing];
+    int next_stage = 0;
+    float *h_res = nullptr;                           // pinned results: 64 x (d + 4) floats
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int parity = 0;                                   // which ft buffer holds f~^k
     std::shared_ptr<Request> lane_req[kLanes];
     int lane_done_iters[kLanes] = {};
-    int64_t lane_clamps_base[kLanes] = {};
+    bool lane_out[kLanes] = {};                       // result copy of the lane not yet collected
     std::deque<hipEvent_t> inflight;                  // events of launched steps
+    std::vector<hipEvent_t> free_events;
     int pending_out = 0;                              // result copies not yet completed
-    Clock::time_point idle_since = Clock::now();
 };
 
 struct Extraction {
     std::shared_ptr<Request> req;
     Pool *pool = nullptr;
-    float *h_out = nullptr;          // pinned d floats
-    unsigned long long *h_clamps = nullptr;
     hipEvent_t ev = nullptr;
     int lane = 0;
     int d = 0;                       // image size of the request's matrix
@@ -105,6 +117,7 @@ struct appga_server {
     std::vector<Extraction> extractions;
     int64_t bytes_in_use = 0;
     std::string loop_error;
+    bool use_graphs = true;    // replay captured graphs (else launch the kernels directly)
 };
 
 namespace {
@@ -147,15 +160,21 @@ void destroy_pool(Pool *p) {
     if (!p) return;
     hipStreamSynchronize(p->stream);
     for (auto ev : p->inflight) hipEventDestroy(ev);
+    for (auto ev : p->free_events) hipEventDestroy(ev);
+    for (auto &st : p->stages) {
+        if (st.ev) hipEventDestroy(st.ev);
+        if (st.h) hipHostFree(st.h);
+    }
     for (auto &gx : p->graph)
         if (gx) hipGraphExecDestroy(gx);
     hipFree(p->arena);
-    hipHostFree(p->h_in);
+    if (p->h_res) hipHostFree(p->h_res);
     hipStreamDestroy(p->stream);
 }
 
-// Captures one APPGA iteration of the pool reading f~ from buffer `cur`.
-hipError_t capture_step(Pool *p, int cur, hipGraphExec_t *out) {
+// Enqueues one APPGA iteration of the pool reading f~ from buffer `cur` on the
+// pool's stream (per-lane theta, forward + ratio, back projection + update).
+hipError_t enqueue_step(Pool *p, int cur) {
     const appga_matrix *mat = p->mat;
     FwdArgs fa{};
     fa.row_ptr = mat->A.row_ptr;
@@ -203,18 +222,23 @@ hipError_t capture_step(Pool *p, int cur, hipGraphExec_t *out) {
     sa.xcd_remap = mat->xcd_remap;
     sa.gf_in = p->gf;
     sa.gf_split = mat->bt_split;
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return e;
     hipError_t e1 = launch_lane_theta(p->lane_k, p->mom, p->theta, p->stream);
     if (e1 == hipSuccess) e1 = launch_forward(mat->A, fa, mat->group_fwd, p->stream);
     if (e1 == hipSuccess && p->gf)
         e1 = launch_back_tiles(mat->bt, mat->AT.vtype, mat->geom.n, mat->A.n_rows, kLanes, mat->bt_remap,
                                mat->bt_split, p->e, p->gf, p->stream);
-    hipError_t e2 = e1 == hipSuccess ? launch_step(mat->AT, sa, mat->group_back, p->stream) : e1;
+    if (e1 == hipSuccess) e1 = launch_step(mat->AT, sa, mat->group_back, p->stream);
+    return e1;
+}
+
+// Captures enqueue_step(p, cur) into an executable graph.
+hipError_t capture_step(Pool *p, int cur, hipGraphExec_t *out) {
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t e1 = enqueue_step(p, cur);
     e = hipStreamEndCapture(p->stream, &graph);
     if (e1 != hipSuccess) return e1;
-    if (e2 != hipSuccess) return e2;
     if (e != hipSuccess) return e;
     e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
@@ -249,9 +273,19 @@ appga_status create_pool(appga_server *srv, const appga_matrix *mat, std::unique
     p->clamps = reinterpret_cast<unsigned long long *>(base + L.clamps);
     p->stage_in = reinterpret_cast<float *>(base + L.stage_in);
     p->stage_out = reinterpret_cast<float *>(base + L.stage_out);
-    e = hipHostMalloc(reinterpret_cast<void **>(&p->h_in), sizeof(float) * 2 * m, hipHostMallocDefault);
+    e = hipSuccess;
+    for (auto &st : p->stages) {
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&st.h), sizeof(float) * 2 * m + 256,
+                                               hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&st.ev, hipEventDisableTiming);
+    }
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&p->h_res), sizeof(float) * (d + 4) * kLanes,
+                          hipHostMallocDefault);
     if (e == hipSuccess) e = launch_fill(p->g, static_cast<size_t>(m) * kLanes, 0.0f, p->stream);
-    if (e == hipSuccess) e = launch_fill(p->gamma, static_cast<size_t>(m) * kLanes, 0.0f, p->stream);
+    // idle lanes: g = 0 with background 1, so A f + gamma never reaches the floor
+    // (a floored bin costs an atomic on the lane's counter)
+    if (e == hipSuccess) e = launch_fill(p->gamma, static_cast<size_t>(m) * kLanes, 1.0f, p->stream);
     for (float *buf : {p->f, p->ft[0], p->ft[1], p->e})
         if (e == hipSuccess)
             e = launch_fill(buf, static_cast<size_t>(buf == p->e ? m : d) * kLanes, 0.0f, p->stream);
@@ -277,8 +311,8 @@ appga_status create_pool(appga_server *srv, const appga_matrix *mat, std::unique
         e = hipMemcpyAsync(p->clamps, cl.data(), sizeof(unsigned long long) * kLanes, hipMemcpyHostToDevice,
                            p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-    if (e == hipSuccess) e = capture_step(p.get(), 0, &p->graph[0]);
-    if (e == hipSuccess) e = capture_step(p.get(), 1, &p->graph[1]);
+    if (e == hipSuccess && srv->use_graphs) e = capture_step(p.get(), 0, &p->graph[0]);
+    if (e == hipSuccess && srv->use_graphs) e = capture_step(p.get(), 1, &p->graph[1]);
     if (e != hipSuccess) {
         destroy_pool(p.get());
         return fail(APPGA_E_DEVICE, "pool set-up failed: %s", hipGetErrorString(e));
@@ -288,24 +322,44 @@ appga_status create_pool(appga_server *srv, const appga_matrix *mat, std::unique
     return APPGA_OK;
 }
 
-// Places request r into lane l of pool p (stream-ordered on the pool's stream).
+// Places request r into lane l of pool p, in stream order on the pool's
+// stream, through the next pinned staging buffer of the ring (no host wait
+// unless that buffer's previous copies are still in flight).
 hipError_t admit(Pool *p, int l, const std::shared_ptr<Request> &r) {
     const appga_matrix *mat = p->mat;
     const int m = mat->A.n_rows, n = mat->geom.n;
-    // data and background into the lane
-    std::memcpy(p->h_in, r->g.data(), sizeof(float) * m);
-    hipError_t e = hipMemcpyAsync(p->stage_in, p->h_in, sizeof(float) * m, hipMemcpyHostToDevice, p->stream);
+    Stage &st = p->stages[p->next_stage];
+    p->next_stage = (p->next_stage + 1) % kStageRing;
+    hipError_t e = hipSuccess;
+    if (st.used) e = hipEventSynchronize(st.ev);
+    if (e != hipSuccess) return e;
+    float *hg = st.h, *hgam = st.h + m;
+    char *tail = reinterpret_cast<char *>(st.h + 2 * m);
+    auto *hlp = reinterpret_cast<LaneParams *>(tail);
+    auto *hmom = reinterpret_cast<double *>(tail + 64);
+    auto *hk = reinterpret_cast<int *>(tail + 128);
+    auto *hcl = reinterpret_cast<unsigned long long *>(tail + 136);
+    std::memcpy(hg, r->g.data(), sizeof(float) * m);
+    if (!r->gamma.empty()) std::memcpy(hgam, r->gamma.data(), sizeof(float) * m);
+    *hlp = LaneParams{static_cast<float>(r->p.lambda1), static_cast<float>(r->p.lambda2),
+                      static_cast<float>(r->p.eps), static_cast<float>(r->p.beta),
+                      static_cast<float>(r->p.fixed_p), 0.f, 0.f, 0.f};
+    hmom[0] = r->p.a;
+    hmom[1] = r->p.b;
+    hmom[2] = r->p.omega;
+    hmom[3] = r->p.momentum == APPGA_MOMENTUM_NONE ? 1.0 : 0.0;
+    *hk = 0;
+    *hcl = 0;
+    // data and background into the lane (the device staging buffer is reused in stream order)
+    e = hipMemcpyAsync(p->stage_in, hg, sizeof(float) * m, hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess) e = launch_lane_scatter(p->stage_in, p->g, m, l, p->stream);
-    if (e != hipSuccess) return e;
-    // wait for the staging copy before the pinned buffer is reused for gamma
-    e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) return e;
-    if (!r->gamma.empty()) {
-        std::memcpy(p->h_in, r->gamma.data(), sizeof(float) * m);
-        e = hipMemcpyAsync(p->stage_in, p->h_in, sizeof(float) * m, hipMemcpyHostToDevice, p->stream);
-        if (e == hipSuccess) e = launch_lane_scatter(p->stage_in, p->gamma, m, l, p->stream);
-    } else {
-        e = launch_lane_fill(p->gamma, m, l, static_cast<float>(r->p.gamma_scalar), p->stream);
+    if (e == hipSuccess) {
+        if (!r->gamma.empty()) {
+            e = hipMemcpyAsync(p->stage_in, hgam, sizeof(float) * m, hipMemcpyHostToDevice, p->stream);
+            if (e == hipSuccess) e = launch_lane_scatter(p->stage_in, p->gamma, m, l, p->stream);
+        } else {
+            e = launch_lane_fill(p->gamma, m, l, static_cast<float>(r->p.gamma_scalar), p->stream);
+        }
     }
     if (e != hipSuccess) return e;
     // initial image of Section 4.1 (ACTc from the host copy of the data, FP64)
@@ -320,21 +374,16 @@ hipError_t admit(Pool *p, int l, const std::shared_ptr<Request> &r) {
         for (int cc = 0; cc < n; ++cc) npfov += (cc - ctr) * (cc - ctr) + (rr - ctr) * (rr - ctr) <= rad2;
     const double tmc = actc / (static_cast<double>(npfov) * mat->geom.n_angles);
     e = launch_lane_disk_init(n, l, tmc, p->f, p->ft[p->parity], p->stream);
-    if (e != hipSuccess) return e;
     // per-lane parameters, iteration counter and clamp counter
-    LaneParams lp{static_cast<float>(r->p.lambda1), static_cast<float>(r->p.lambda2),
-                  static_cast<float>(r->p.eps), static_cast<float>(r->p.beta),
-                  static_cast<float>(r->p.fixed_p), 0.f, 0.f, 0.f};
-    double mom[4] = {r->p.a, r->p.b, r->p.omega, r->p.momentum == APPGA_MOMENTUM_NONE ? 1.0 : 0.0};
-    int k0 = 0;
-    unsigned long long c0 = 0;
-    e = hipMemcpyAsync(p->lp + l, &lp, sizeof(lp), hipMemcpyHostToDevice, p->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->mom + 4 * l, mom, sizeof(mom), hipMemcpyHostToDevice, p->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->lane_k + l, &k0, sizeof(int), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->lp + l, hlp, sizeof(LaneParams), hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(p->clamps + l, &c0, sizeof(c0), hipMemcpyHostToDevice, p->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // small pageable copies
+        e = hipMemcpyAsync(p->mom + 4 * l, hmom, 4 * sizeof(double), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->lane_k + l, hk, sizeof(int), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->clamps + l, hcl, sizeof(unsigned long long), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(st.ev, p->stream);
     if (e != hipSuccess) return e;
+    st.used = true;
     p->lane_req[l] = r;
     p->lane_done_iters[l] = 0;
     return hipSuccess;
@@ -405,7 +454,7 @@ bool loop_pass(appga_server *srv) {
         Pool *p = it->second.get();
         const int cap = std::max(1, std::min(kLanes, srv->cfg.slots_per_matrix));
         for (int l = 0; l < cap && !q.empty(); ++l) {
-            if (p->lane_req[l]) continue;
+            if (p->lane_req[l] || p->lane_out[l]) continue;
             auto r = q.front();
             q.pop_front();
             hipError_t e = admit(p, l, r);
@@ -416,20 +465,28 @@ bool loop_pass(appga_server *srv) {
             worked = true;
         }
     }
-    // 3. one step of every pool with occupied lanes (at most 3 steps in flight per pool)
+    // 3. one more step of every pool with occupied lanes and fewer than kDepth
+    //    steps in flight (never waits: a busy pool is visited again next pass)
     for (auto &pp : srv->pools) {
         Pool *p = pp.second.get();
-        if (!pool_active(p)) continue;
-        while (p->inflight.size() >= 3) {
-            hipEventSynchronize(p->inflight.front());
-            hipEventDestroy(p->inflight.front());
+        while (!p->inflight.empty() && hipEventQuery(p->inflight.front()) == hipSuccess) {
+            p->free_events.push_back(p->inflight.front());
             p->inflight.pop_front();
         }
-        hipError_t e = hipGraphLaunch(p->graph[p->parity], p->stream);
+        if (!pool_active(p) || p->inflight.size() >= static_cast<size_t>(kDepth)) continue;
         hipEvent_t ev = nullptr;
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        hipError_t e = hipSuccess;
+        if (!p->free_events.empty()) {
+            ev = p->free_events.back();
+            p->free_events.pop_back();
+        } else {
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        }
+        if (e == hipSuccess)
+            e = p->graph[p->parity] ? hipGraphLaunch(p->graph[p->parity], p->stream) : enqueue_step(p, p->parity);
         if (e == hipSuccess) e = hipEventRecord(ev, p->stream);
         if (e != hipSuccess) {
+            if (ev) p->free_events.push_back(ev);
             srv->loop_error = hipGetErrorString(e);
             for (int l = 0; l < kLanes; ++l)
                 if (p->lane_req[l]) {
@@ -441,7 +498,8 @@ bool loop_pass(appga_server *srv) {
         p->inflight.push_back(ev);
         p->parity ^= 1;
         worked = true;
-        // lanes whose budget is done: copy out
+        // lanes whose budget is done: copy out into the lane's pinned result slot
+        const int d = p->mat->A.n_cols;
         for (int l = 0; l < kLanes; ++l) {
             auto &r = p->lane_req[l];
             if (!r) continue;
@@ -450,30 +508,29 @@ bool loop_pass(appga_server *srv) {
             x.req = r;
             x.pool = p;
             x.lane = l;
-            const int d = p->mat->A.n_cols;
             x.d = d;
-            hipError_t ee = hipHostMalloc(reinterpret_cast<void **>(&x.h_out), sizeof(float) * d + 64,
-                                          hipHostMallocDefault);
-            x.h_clamps = reinterpret_cast<unsigned long long *>(x.h_out + d + (d & 1));
-            if (ee == hipSuccess) ee = launch_lane_gather(p->f, p->stage_out, d, l, p->stream);
+            float *h_out = p->h_res + static_cast<size_t>(l) * (d + 4);
+            auto *h_cl = reinterpret_cast<unsigned long long *>(h_out + d + (d & 1));
+            hipError_t ee = launch_lane_gather(p->f, p->stage_out, d, l, p->stream);
             if (ee == hipSuccess)
-                ee = hipMemcpyAsync(x.h_out, p->stage_out, sizeof(float) * d, hipMemcpyDeviceToHost, p->stream);
+                ee = hipMemcpyAsync(h_out, p->stage_out, sizeof(float) * d, hipMemcpyDeviceToHost, p->stream);
             if (ee == hipSuccess)
-                ee = hipMemcpyAsync(x.h_clamps, p->clamps + l, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                ee = hipMemcpyAsync(h_cl, p->clamps + l, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                     p->stream);
             if (ee == hipSuccess) ee = hipEventCreateWithFlags(&x.ev, hipEventDisableTiming);
             if (ee == hipSuccess) ee = hipEventRecord(x.ev, p->stream);
             if (ee != hipSuccess) {
+                if (x.ev) hipEventDestroy(x.ev);
                 finish(srv, r, fail(APPGA_E_DEVICE, "result copy failed: %s", hipGetErrorString(ee)));
-                if (x.h_out) hipHostFree(x.h_out);
             } else {
                 ++p->pending_out;
+                p->lane_out[l] = true;
                 srv->extractions.push_back(x);
             }
-            r.reset();  // lane reusable (stream order protects the copy)
+            r.reset();  // the lane takes a new request once its result is collected
         }
     }
-    // 4. completed extractions
+    // 4. completed result copies
     for (size_t i = 0; i < srv->extractions.size();) {
         Extraction &x = srv->extractions[i];
         if (hipEventQuery(x.ev) != hipSuccess) {
@@ -481,20 +538,22 @@ bool loop_pass(appga_server *srv) {
             continue;
         }
         const int d = x.d;
-        --x.pool->pending_out;
+        const float *h_out = x.pool->h_res + static_cast<size_t>(x.lane) * (d + 4);
+        const auto *h_cl = reinterpret_cast<const unsigned long long *>(h_out + d + (d & 1));
         auto r = x.req;
-        r->result.assign(x.h_out, x.h_out + d);
+        r->result.assign(h_out, h_out + d);
         r->stats.iterations_done = r->p.iterations;
         r->stats.objective0 = 0.0;
         r->stats.objective = 0.0;
         r->stats.re = 0.0;
-        r->stats.guard_clamps = static_cast<int64_t>(*x.h_clamps);
+        r->stats.guard_clamps = static_cast<int64_t>(*h_cl);
         r->stats.seconds = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
         bool finite = true;
         for (float v : r->result)
             if (!std::isfinite(v)) finite = false;
         hipEventDestroy(x.ev);
-        hipHostFree(x.h_out);
+        --x.pool->pending_out;
+        x.pool->lane_out[x.lane] = false;
         finish(srv, r, finite ? APPGA_OK : APPGA_E_NONFINITE);
         srv->extractions.erase(srv->extractions.begin() + static_cast<long>(i));
         worked = true;
@@ -511,10 +570,13 @@ void run_loop(appga_server *srv) {
         for (auto &wq : srv->waiting) busy = busy || !wq.second.empty();
         std::unique_lock<std::mutex> lk(srv->mu);
         if (srv->stopping && !busy && srv->arrivals.empty()) break;
-        if (!worked && !busy && srv->arrivals.empty())
+        if (!worked && !busy && srv->arrivals.empty()) {
             srv->cv_work.wait_for(lk, std::chrono::milliseconds(5));
-        else if (!worked && srv->extractions.empty() == false)
+        } else if (!worked) {
+            // device work in flight and nothing to launch: poll again at once
+            lk.unlock();
             std::this_thread::yield();
+        }
     }
     for (auto &pp : srv->pools) destroy_pool(pp.second.get());
     srv->pools.clear();
@@ -538,6 +600,8 @@ extern "C" appga_status appga_server_start(appga_ctx *ctx, const appga_server_cf
     auto *srv = new appga_server();
     srv->ctx = ctx;
     srv->cfg = *cfg;
+    const char *gs = std::getenv("APPGA_SERVER_GRAPHS");
+    srv->use_graphs = !(gs && gs[0] == '0');
     srv->loop = std::thread(run_loop, srv);
     *out = srv;
     return APPGA_OK;

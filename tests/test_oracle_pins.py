@@ -320,6 +320,29 @@ def test_identity_system():
     assert abs(h["obj"][-1] - np.sum(g - g * np.log(g))) <= 1e-13 * np.abs(h["obj"][-1])
 
 
+def test_round_f32_diagnostic():
+    """The FP32-rounding diagnostic changes nothing where every stored value is an
+    FP32 number (A = I, integer counts: each iterate is g exactly), and moves a real
+    problem by an FP32-size amount."""
+    n = 4
+    d = n * n
+    A = synth.SparseMatrix(d, d, np.arange(d + 1, dtype=np.int64), np.arange(d, dtype=np.int32),
+                           np.ones(d))
+    g = rng(12).integers(1, 50, d).astype(np.float64)
+    f1 = np.full(d, 2.0)
+    kw = dict(momentum=oracle.MOMENTUM_NONE, f_init=f1)
+    exact = oracle.appga(A, n, 1, g, np.zeros(d), 0.0, 0.0, 1e-3, 1.0, 5, **kw)["f"]
+    rounded = oracle.appga(A, n, 1, g, np.zeros(d), 0.0, 0.0, 1e-3, 1.0, 5, round_f32=True, **kw)["f"]
+    np.testing.assert_array_equal(exact, rounded)
+    pr = synth.config_problem("c1_64")
+    args = (pr.A, 64, 90, pr.g[0], pr.gamma[0], 0.05, 0.05, 1e-3, 0.5, 10)
+    f0 = oracle.appga(*args)["f"]
+    f1r = oracle.appga(*args, round_f32=True)["f"]
+    gap = np.linalg.norm(f1r - f0) / np.linalg.norm(f0)
+    assert 1e-9 < gap < 1e-5
+    assert np.abs(f1r - f1r.astype(np.float32)).max() == 0.0   # the output is an FP32 image
+
+
 def test_floor_rule_identity_system():
     """Momentum can push A ft + gamma below zero; the oracle floors it at 1e-6 gamma
     (1e-30 when gamma = 0) and counts the floored bins.  With A = I the third iterate is
