@@ -235,6 +235,7 @@ def main():
     ctx = ap.appga_create(0)
     mat = ap.load_matrix(ctx, A, geom, args.storage)
     info = ap.appga_matrix_info(mat)
+    tuning = ap.appga_tune(ctx, mat)   # the choice the load made (re-timed)
     gam_scalar = [float(pr.gamma[b][0]) for b in range(B)]
     params = [ap.make_params(lam=0.02, eps=1e-3, omega=0.5, iterations=300,
                              gamma_scalar=gam_scalar[b]) for b in range(B)]
@@ -317,6 +318,8 @@ def main():
     if not args.no_projector:
         log("single-solve projector leg (256^2, FP32 matrix)")
         projector = projector_leg(ap, torch, ctx, pr256, mat256, max(20, min(args.steps, 100)))
+        t256 = ap.appga_tune(ctx, mat256, ap.APPGA_TUNE_SINGLE)
+        projector["lanes_per_row"] = {"forward": t256["group_fwd"], "back": t256["group_back"]}
 
     serving = None
     if args.serve_requests > 0 and not args.profile:
@@ -372,6 +375,7 @@ def main():
         "serving": serving,
         "projector_single_256": projector,
         "matrix_bytes": info,
+        "tuning": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tuning.items()},
         "objective_lane0": stats[0]["objective"],
     }
     print(json.dumps(line), flush=True)

@@ -135,6 +135,24 @@ appga_status appga_free_system_matrix(appga_ctx *ctx, appga_matrix *mat);
 appga_status appga_matrix_info(const appga_matrix *mat, int64_t *nnz, int64_t *bytes_a,
                                int64_t *bytes_at, int32_t *storage);
 
+/* Launch-configuration autotuner.  Times the candidate launch configurations
+ * of the projector kernels for `mat` on the device and keeps the fastest:
+ * APPGA_TUNE_SINGLE -- lanes per matrix row (4..64) of the single-solve
+ * forward and back projection kernels; APPGA_TUNE_BATCH -- workgroups of the
+ * batched forward grid and the XCD tile order of the batched step kernel.
+ * Parameters pinned by the environment (APPGA_GROUP_FWD, APPGA_GROUP_BACK,
+ * APPGA_FWD_WGS, APPGA_XCD_REMAP) are not searched.  Results only change
+ * speed, never values.  appga_load_system_matrix runs it (both flags) unless
+ * APPGA_AUTOTUNE=0.  *out (nullable) receives the choice and the timings
+ * (microseconds per launch; 0 = not searched).  Synchronises the context's
+ * stream; APPGA_E_BUSY while server requests use the matrix. */
+enum { APPGA_TUNE_SINGLE = 1, APPGA_TUNE_BATCH = 2 };
+typedef struct {
+    int32_t group_fwd, group_back, fwd_wgs, xcd_remap;
+    double us_fwd_single, us_back_single, us_fwd_batch, us_step_batch;
+} appga_tuning;
+appga_status appga_tune(appga_ctx *ctx, appga_matrix *mat, int32_t flags, appga_tuning *out);
+
 /* Writes the values A holds after storage rounding (dequantised, FP64) in
  * the caller's CSR order: nnz entries. */
 appga_status appga_matrix_dequantized(const appga_matrix *mat, double *values_out);

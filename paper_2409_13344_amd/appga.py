@@ -94,6 +94,7 @@ _SIGS = {
     "appga_set_kernel_timing": [P, I32],
     "appga_kernel_times": [P, I32, P, I32, P, P, C.POINTER(I32)],
     "appga_server_footprint": [P, C.POINTER(I64)],
+    "appga_tune": [P, P, I32, P],
     "appga_server_start": [P, C.POINTER(appga_server_cfg), PP],
     "appga_submit": [P, P, P, P, C.POINTER(appga_params), C.POINTER(U64)],
     "appga_wait": [P, U64, P, C.POINTER(appga_stats), I32],
@@ -343,6 +344,24 @@ def appga_kernel_times(ctx) -> Dict[str, dict]:
 
 
 # ---------------------------------------------------------------- serving ---
+
+class appga_tuning(C.Structure):
+    _fields_ = [("group_fwd", I32), ("group_back", I32), ("fwd_wgs", I32), ("xcd_remap", I32),
+                ("us_fwd_single", D), ("us_back_single", D), ("us_fwd_batch", D),
+                ("us_step_batch", D)]
+
+    def to_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+APPGA_TUNE_SINGLE, APPGA_TUNE_BATCH = 1, 2
+
+
+def appga_tune(ctx, mat, flags: int = APPGA_TUNE_SINGLE | APPGA_TUNE_BATCH) -> dict:
+    t = appga_tuning()
+    _call("appga_tune", ctx, mat, flags, C.byref(t))
+    return t.to_dict()
+
 
 def appga_server_footprint(mat) -> int:
     b = I64()

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libappga.so")
-SOURCES = ["kernels.hip", "appga_api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "appga_api.cpp", "server.cpp", "tune.cpp"]
 ARCH = os.environ.get("APPGA_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

@@ -42,19 +42,6 @@ void clear_error() { g_last_error.clear(); }
 
 }  // namespace appga
 
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return fail(APPGA_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
-    } while (0)
-
-#define ST_TRY(expr)                        \
-    do {                                    \
-        appga_status s_ = (expr);           \
-        if (s_ != APPGA_OK) return s_;      \
-    } while (0)
-
 extern "C" const char *appga_last_error(void) { return g_last_error.c_str(); }
 
 // --------------------------------------------------------- value coding ---
@@ -584,11 +571,23 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
     // the remap needs the tile grid (tx x tx) to split into 2 x 4 equal blocks
     const int tx = (geom->n + 3) / 4;
     const bool remap_ok = tx % 4 == 0;
+    mat->remap_ok = remap_ok ? 1 : 0;
     mat->xcd_remap = (remap_ok && env_int("APPGA_XCD_REMAP", 1)) ? 1 : 0;
     mat->bt_remap = (mat->bt.valid && mat->bt.tiles_x % 4 == 0 && env_int("APPGA_XCD_REMAP", 1)) ? 1 : 0;
     mat->bt_split = mat->bt.valid ? std::max(1, std::min(mat->bt.n_groups,
                                                          env_int("APPGA_BACK_SPLIT", back_tiles_split(mat->bt))))
                                   : 1;
+    if (env_int("APPGA_AUTOTUNE", 1)) {
+        const appga_status ts = tune_matrix(ctx, mat, APPGA_TUNE_SINGLE | APPGA_TUNE_BATCH, nullptr);
+        if (ts != APPGA_OK) {
+            free_csr(mat->A);
+            free_csr(mat->AT);
+            free_back_tiles(mat->bt);
+            hipFree(mat->lam);
+            delete mat;
+            return ts;
+        }
+    }
     *out = mat;
     return APPGA_OK;
 }

@@ -39,6 +39,7 @@ struct appga_matrix {
     std::vector<int32_t> user_col;
     int group_fwd = 16, group_back = 16;
     int xcd_remap = 0;
+    int remap_ok = 0;                  // the 4 x 4 tile grid splits into 2 x 4 XCD blocks
     int bt_remap = 0;                  // XCD remap of the 8 x 8 tile grid
     int bt_split = 1;                  // workgroups (partial sums) per tile of the back projection
     int fwd_wgs = 2048;                // batched forward: workgroups of the row-strided grid
@@ -69,6 +70,21 @@ struct appga_solve {
     std::chrono::steady_clock::time_point t0;
 };
 
+// Returns APPGA_E_DEVICE (with the failing call in the message) when a HIP
+// call fails, and propagates a failed appga_status.
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return ::appga::fail(APPGA_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define ST_TRY(expr)                        \
+    do {                                    \
+        appga_status s_ = (expr);           \
+        if (s_ != APPGA_OK) return s_;      \
+    } while (0)
+
 namespace appga {
 
 appga_status fail(appga_status st, const char *fmt, ...);
@@ -84,6 +100,7 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
                         hipStream_t st, appga_solve **out);
 appga_status sess_step(appga_solve *s, int n_iters);
 appga_status sess_end(appga_solve *s, float *d_out, appga_stats *stats, bool free_session);
+appga_status tune_matrix(appga_ctx *ctx, appga_matrix *mat, int flags, appga_tuning *out);
 void sess_free(appga_solve *s);
 
 }  // namespace appga

@@ -201,13 +201,29 @@ __device__ __forceinline__ float gather_dot_lanes64(__amdgpu_buffer_rsrc_t cr,
 // B = 1: partial dot product of lane gl of a G-lane group over the stored
 // entries [k0, k1): lane gl takes chunks gl, gl + G, ...; the gather offset is
 // per lane.
+// Two chunks per round trip (their index and value loads issued together, then
+// their 16 gathers), so that each lane has twice the loads in flight; the
+// products are added in chunk order.
 template <typename IT, int VT, int G>
 __device__ __forceinline__ float gather_dot_group(const IT *__restrict__ col,
                                                   const void *__restrict__ val,
                                                   __amdgpu_buffer_rsrc_t xr, int k0, int k1,
                                                   int gl) {
     float acc = 0.0f;
-    for (int k = k0 + gl * kChunk; k < k1; k += G * kChunk) {
+    int k = k0 + gl * kChunk;
+    for (; k + G * kChunk < k1; k += 2 * G * kChunk) {
+        uint32_t c[16];
+        float v[16], xv[16];
+        load_cols8<IT>(col, k, c);
+        load_cols8<IT>(col, k + G * kChunk, c + 8);
+        load_vals8<VT>(val, k, v);
+        load_vals8<VT>(val, k + G * kChunk, v + 8);
+#pragma unroll
+        for (int t = 0; t < 16; ++t) xv[t] = buf_load(xr, 4u * c[t], 0u);
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc = fmaf(v[t], xv[t], acc);
+    }
+    if (k < k1) {
         uint32_t c[8];
         float v[8], xv[8];
         load_cols8<IT>(col, k, c);

@@ -411,3 +411,38 @@ def test_errors_through_the_abi(ctx, c2, c2_mat):
     with pytest.raises(ap.AppgaError) as ei:
         ap.appga_load_system_matrix(ctx, 128, 168, 200, c2.A.row_ptr, bad, c2.A.val)
     assert ei.value.status == -2
+
+
+# ------------------------------------------------------------ autotuner ---
+
+def test_autotuner_choices_and_values(ctx, c2):
+    """The autotuner picks launch configurations only: a solve on a tuned matrix agrees
+    with one on the untuned (heuristic) configuration to FP32 rounding."""
+    import os
+    say("autotuner")
+    saved = os.environ.get("APPGA_AUTOTUNE")
+    os.environ["APPGA_AUTOTUNE"] = "0"
+    try:
+        plain = ap.load_matrix(ctx, c2.A, c2.geom, "f32")
+    finally:
+        if saved is None:
+            os.environ.pop("APPGA_AUTOTUNE", None)
+        else:
+            os.environ["APPGA_AUTOTUNE"] = saved
+    tuned = ap.load_matrix(ctx, c2.A, c2.geom, "f32")
+    try:
+        t = ap.appga_tune(ctx, tuned)
+        say("  choice %s" % t)
+        assert t["group_fwd"] in (4, 8, 16, 32, 64) and t["group_back"] in (4, 8, 16, 32, 64)
+        assert t["fwd_wgs"] in (1024, 2048, 4096, 8192) and t["xcd_remap"] in (0, 1)
+        assert t["us_fwd_single"] > 0 and t["us_back_single"] > 0 and t["us_fwd_batch"] > 0
+        p = ap.make_params(lam=0.02, eps=1e-3, omega=0.5, iterations=100)
+        f0, _ = ap.appga_reconstruct(ctx, plain, c2.geom.d, c2.g[0], c2.gamma[0], p)
+        f1, _ = ap.appga_reconstruct(ctx, tuned, c2.geom.d, c2.g[0], c2.gamma[0], p)
+        assert rel_l2(f1, f0) <= 1e-6
+        with pytest.raises(ap.AppgaError) as ei:
+            ap.appga_tune(ctx, tuned, 4)
+        assert ei.value.status == -1
+    finally:
+        ap.appga_free_system_matrix(ctx, plain)
+        ap.appga_free_system_matrix(ctx, tuned)
