@@ -80,8 +80,11 @@ typedef struct {
  * Domain (APPGA_E_DOMAIN otherwise): lambda1, lambda2 >= 0; eps > 0;
  * omega in (0, 1]; a > 0, and a < 1/2 when omega = 1 (Lemma 8); b not equal to
  * -a k^omega for any k >= 1; beta > 0; iterations >= 0; fixed_p > 0 in FIXED
- * mode; gamma_scalar >= 0.  monitor_every > 0 computes the FP64 objective
- * every that many iterations (0 = only at the start and the end). */
+ * mode; gamma_scalar >= 0.  monitor_every = M > 0 (solve sessions; the first
+ * solve's value counts for a batch) computes the FP64 objective Phi(f^k) of
+ * every solve at k = 1, M + 1, 2M + 1, ... (one extra forward projection and
+ * a stream synchronisation each), read with appga_solve_history; 0 = only at
+ * the start and the end. */
 typedef struct {
     double lambda1, lambda2, eps, omega, a, b, beta;
     int32_t iterations, momentum, precond, precond_freeze_iter, monitor_every;
@@ -202,6 +205,12 @@ appga_status appga_solve_begin(appga_ctx *ctx, const appga_matrix *mat, int32_t 
                                const float *d_g, const float *d_gamma, const appga_params *params,
                                const float *d_f_init, void *hip_stream, appga_solve **out);
 appga_status appga_solve_step(appga_solve *s, int32_t n_iters);
+/* Objective history of solve `solve` (sessions with monitor_every > 0, before
+ * appga_solve_end): *count = number of monitored iterations so far; the first
+ * min(count, cap) pairs (k, Phi(f^k) in FP64), f^1 first, go to iters_out and
+ * obj_out (host arrays of cap entries; may be NULL when cap = 0). */
+appga_status appga_solve_history(const appga_solve *s, int32_t solve, int32_t cap, int32_t *iters_out,
+                                 double *obj_out, int32_t *count);
 appga_status appga_solve_end(appga_solve *s, float *d_out, appga_stats *stats);
 
 /* Device operators (each one kernel of the iteration, for tests and timing).

@@ -95,6 +95,7 @@ _SIGS = {
     "appga_kernel_times": [P, I32, P, I32, P, P, C.POINTER(I32)],
     "appga_server_footprint": [P, C.POINTER(I64)],
     "appga_tune": [P, P, I32, P],
+    "appga_solve_history": [P, I32, I32, P, P, C.POINTER(I32)],
     "appga_server_start": [P, C.POINTER(appga_server_cfg), PP],
     "appga_submit": [P, P, P, P, C.POINTER(appga_params), C.POINTER(U64)],
     "appga_wait": [P, U64, P, C.POINTER(appga_stats), I32],
@@ -280,6 +281,16 @@ def appga_solve_begin(ctx, mat, g_t, gamma_t, params: Sequence[appga_params], f_
 
 def appga_solve_step(sess, n_iters: int) -> None:
     _call("appga_solve_step", sess, n_iters)
+
+
+def appga_solve_history(sess, solve: int):
+    """(iterations k, Phi(f^k)) of one solve of a session with monitor_every > 0."""
+    n = I32()
+    _call("appga_solve_history", sess, solve, 0, None, None, C.byref(n))
+    ks = np.empty(n.value, dtype=np.int32)
+    obj = np.empty(n.value, dtype=np.float64)
+    _call("appga_solve_history", sess, solve, n.value, _ptr(ks), _ptr(obj), C.byref(n))
+    return ks, obj
 
 
 def appga_solve_end(sess, out_t, B: int) -> List[dict]:

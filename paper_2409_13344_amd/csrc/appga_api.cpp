@@ -710,6 +710,9 @@ static appga_status sess_alloc(appga_solve *s) {
     const size_t o_th = take(sizeof(float) * (s->theta_cap + 2) * Bp);
     const size_t o_part = take(sizeof(double) * s->part_len);
     const size_t o_red = take(sizeof(double) * 4 * Bp);
+    const bool mon = s->monitor_every > 0;
+    const size_t o_mpart = mon ? take(sizeof(double) * s->part_len) : 0;
+    const size_t o_mred = mon ? take(sizeof(double) * 4 * Bp) : 0;
     const size_t o_cl = take(sizeof(unsigned long long) * Bp);
     const size_t o_tmc = take(sizeof(double) * Bp);
     HIP_TRY(hipMalloc(&s->arena, off));
@@ -727,6 +730,8 @@ static appga_status sess_alloc(appga_solve *s) {
     s->theta = reinterpret_cast<float *>(base + o_th);
     s->part = reinterpret_cast<double *>(base + o_part);
     s->red = reinterpret_cast<double *>(base + o_red);
+    s->mpart = mon ? reinterpret_cast<double *>(base + o_mpart) : nullptr;
+    s->mred = mon ? reinterpret_cast<double *>(base + o_mred) : nullptr;
     s->clamps = reinterpret_cast<unsigned long long *>(base + o_cl);
     s->tmc = reinterpret_cast<double *>(base + o_tmc);
     return APPGA_OK;
@@ -747,7 +752,10 @@ static appga_status sess_theta(appga_solve *s, int k0) {
 }
 
 // FP64 objective Phi(x) per solve (Section 2.1) into host vector out.
-appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> &out) {
+appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> &out,
+                            double *part = nullptr, double *red = nullptr) {
+    if (!part) part = s->part;
+    if (!red) red = s->red;
     const appga_matrix *mat = s->mat;
     const int B = s->B;
     const int m = mat->A.n_rows, n = mat->geom.n;
@@ -757,7 +765,7 @@ appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> 
     fa.val = mat->A.val;
     fa.row_scale = mat->A.row_scale;
     fa.col32 = mat->A.col32;
-        fa.nnz_padded = mat->A.nnz_padded;
+    fa.nnz_padded = mat->A.nnz_padded;
     fa.m = m;
     fa.n_x = mat->A.n_cols;
     fa.B = B;
@@ -770,12 +778,12 @@ appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> 
     fa.mode = FM_PROJ;
     HIP_TRY(timed_launch(s->ctx, "forward_proj", s->st,
                          [&] { return launch_forward(mat->A, fa, mat->group_fwd, s->st); }));
-    HIP_TRY(launch_fidelity_terms(m, B, s->e, s->g, s->gamma, s->gamma_lane, s->part, s->st));
-    HIP_TRY(launch_reduce_partials(s->part, fidelity_blocks(m), B, 1, s->red, s->st));
-    HIP_TRY(launch_reg_value(n, B, x, s->lp, s->part, s->st));
-    HIP_TRY(launch_reduce_partials(s->part, reg_value_blocks(n), B, 1, s->red + B, s->st));
+    HIP_TRY(launch_fidelity_terms(m, B, s->e, s->g, s->gamma, s->gamma_lane, part, s->st));
+    HIP_TRY(launch_reduce_partials(part, fidelity_blocks(m), B, 1, red, s->st));
+    HIP_TRY(launch_reg_value(n, B, x, s->lp, part, s->st));
+    HIP_TRY(launch_reduce_partials(part, reg_value_blocks(n), B, 1, red + B, s->st));
     std::vector<double> h(2 * B);
-    HIP_TRY(hipMemcpyAsync(h.data(), s->red, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s->st));
+    HIP_TRY(hipMemcpyAsync(h.data(), red, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s->st));
     HIP_TRY(hipStreamSynchronize(s->st));
     out.resize(B);
     for (int b = 0; b < B; ++b) out[b] = h[b] + h[B + b];
@@ -803,6 +811,7 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
     s->prm.assign(params, params + B);
     s->has_gamma = d_gamma != nullptr;
     s->need_pbuf = params[0].precond == APPGA_PRECOND_EM_FROZEN;
+    s->monitor_every = params[0].monitor_every;
     s->t0 = std::chrono::steady_clock::now();
     appga_status rs = sess_alloc(s);
     if (rs != APPGA_OK) {
@@ -894,6 +903,10 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
     s->k = 1;
     rs = sess_theta(s, 0);
     if (rs == APPGA_OK) rs = sess_objective(s, s->f, s->obj0);
+    if (rs == APPGA_OK && s->monitor_every > 0) {
+        s->hist_k.push_back(1);
+        s->hist_obj.insert(s->hist_obj.end(), s->obj0.begin(), s->obj0.end());
+    }
     if (rs != APPGA_OK) return bail(rs);
     *out = s;
     return APPGA_OK;
@@ -972,6 +985,12 @@ appga_status sess_step(appga_solve *s, int n_iters) {
         s->cur ^= 1;
         s->k += 1;
         s->re_valid = (it == n_iters - 1);
+        if (s->monitor_every > 0 && (s->k - 1) % s->monitor_every == 0) {
+            std::vector<double> obj;
+            ST_TRY(sess_objective(s, s->f, obj, s->mpart, s->mred));
+            s->hist_k.push_back(s->k);
+            s->hist_obj.insert(s->hist_obj.end(), obj.begin(), obj.end());
+        }
     }
     return APPGA_OK;
 }
@@ -1044,6 +1063,21 @@ extern "C" appga_status appga_solve_begin(appga_ctx *ctx, const appga_matrix *ma
 extern "C" appga_status appga_solve_step(appga_solve *s, int32_t n_iters) {
     clear_error();
     return sess_step(s, n_iters);
+}
+
+extern "C" appga_status appga_solve_history(const appga_solve *s, int32_t solve, int32_t cap,
+                                            int32_t *iters_out, double *obj_out, int32_t *count) {
+    clear_error();
+    if (!s || !count) return fail(APPGA_E_INVALID_ARG, "NULL session or count");
+    if (solve < 0 || solve >= s->B) return fail(APPGA_E_INVALID_ARG, "solve index %d out of range", solve);
+    const int32_t n = static_cast<int32_t>(s->hist_k.size());
+    *count = n;
+    if (cap > 0 && (!iters_out || !obj_out)) return fail(APPGA_E_INVALID_ARG, "NULL output arrays");
+    for (int32_t i = 0; i < std::min(n, cap); ++i) {
+        iters_out[i] = s->hist_k[i];
+        obj_out[i] = s->hist_obj[static_cast<size_t>(i) * s->B + solve];
+    }
+    return APPGA_OK;
 }
 
 extern "C" appga_status appga_solve_end(appga_solve *s, float *d_out, appga_stats *stats) {

@@ -67,6 +67,12 @@ struct appga_solve {
     int k = 1, cur = 0;
     bool re_valid = false;
     std::vector<double> obj0;
+    // objective monitor (monitor_every > 0): its own reduction buffers, and the
+    // history of (k, Phi(f^k)) per solve, f^1 first
+    int monitor_every = 0;
+    double *mpart = nullptr, *mred = nullptr;
+    std::vector<int32_t> hist_k;
+    std::vector<double> hist_obj;   // [entry][B]
     std::chrono::steady_clock::time_point t0;
 };
 

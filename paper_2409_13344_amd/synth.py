@@ -29,7 +29,7 @@ from typing import Dict, List, Optional
 import numpy as np
 
 __all__ = [
-    "Geometry", "SparseMatrix", "Problem", "siddon_matrix", "ellipse_phantom",
+    "Geometry", "SparseMatrix", "Problem", "siddon_matrix", "ellipse_phantom", "disc_phantom",
     "make_problem", "config_problem", "CONFIGS", "chord_length_square",
 ]
 
@@ -196,6 +196,21 @@ def ellipse_phantom(n: int, rng: np.random.Generator, n_ellipses: int = 6) -> np
     return img.reshape(-1)
 
 
+def disc_phantom(n: int, rng: np.random.Generator) -> np.ndarray:
+    """A uniform disc (activity 1, zero background), membership by pixel centre.
+
+    Radius U[0.3, 0.45] * N and centre offset uniform in the disk of radius
+    0.05 * N about the image centre, so the disc stays inside the field of view.
+    """
+    xs = np.arange(n, dtype=np.float64) - (n - 1) / 2.0
+    X, Y = np.meshgrid(xs, xs)
+    rad = rng.uniform(0.3, 0.45) * n
+    off = 0.05 * n * math.sqrt(rng.uniform())
+    ang = rng.uniform(0.0, 2.0 * math.pi)
+    cx, cy = off * math.cos(ang), off * math.sin(ang)
+    return ((X - cx) ** 2 + (Y - cy) ** 2 <= rad * rad).astype(np.float64).reshape(-1)
+
+
 def _column_sums(A: SparseMatrix) -> np.ndarray:
     s = np.zeros(A.n_cols, dtype=np.float64)
     np.add.at(s, A.col, A.val)
@@ -203,12 +218,14 @@ def _column_sums(A: SparseMatrix) -> np.ndarray:
 
 
 def make_problem(geom: Geometry, seeds: List[int], tc=1e6, rf=0.1,
-                 A: Optional[SparseMatrix] = None, tc_range=None, rf_range=None) -> Problem:
+                 A: Optional[SparseMatrix] = None, tc_range=None, rf_range=None,
+                 phantom: str = "ellipses") -> Problem:
     """Phantoms, scaled expected data and Poisson counts for each seed.
 
     Per seed: rng = default_rng(seed); if ``tc_range``/``rf_range`` are given
     the total counts are 10**U[log10 lo, log10 hi] and the background fraction
-    U[lo, hi] (drawn first, in that order); then the phantom is drawn.  f_true
+    U[lo, hi] (drawn first, in that order); then the phantom ("ellipses" or
+    "disc") is drawn.  f_true
     is scaled so that sum(A f_true) = (1 - rf) * TC and gamma_i = rf * TC / m in
     every bin; g = Poisson(A f_true + gamma) from default_rng(seed + 10**6).
     g and gamma are rounded to float32 once, here, so every consumer sees the
@@ -234,7 +251,12 @@ def make_problem(geom: Geometry, seeds: List[int], tc=1e6, rf=0.1,
             tck = 10.0 ** rng.uniform(math.log10(tc_range[0]), math.log10(tc_range[1]))
         if rf_range is not None:
             rfk = rng.uniform(rf_range[0], rf_range[1])
-        f0 = ellipse_phantom(geom.n, rng)
+        if phantom == "ellipses":
+            f0 = ellipse_phantom(geom.n, rng)
+        elif phantom == "disc":
+            f0 = disc_phantom(geom.n, rng)
+        else:
+            raise ValueError("unknown phantom %r" % phantom)
         f0 *= (1.0 - rfk) * tck / float(colsum @ f0)
         mean = np.zeros(m, dtype=np.float64)
         np.add.at(mean, rows, A.val * f0[A.col])

@@ -90,3 +90,18 @@ def test_ranges_per_seed():
     p = synth.make_problem(geom, list(range(10)), tc_range=(1e5, 1e7), rf_range=(0.05, 0.2))
     assert np.all((p.tc >= 1e5) & (p.tc <= 1e7)) and np.all((p.rf >= 0.05) & (p.rf <= 0.2))
     assert len(np.unique(p.tc)) == 10
+
+
+def test_disc_phantom_inside_fov_and_scaled():
+    geom = synth.Geometry(32, 48, 30)
+    pr = synth.make_problem(geom, [7, 8], tc=1e5, rf=0.1, phantom="disc")
+    for k in range(2):
+        f = pr.f_true[k].reshape(32, 32)
+        vals = np.unique(f[f > 0])
+        assert len(vals) == 1                      # uniform activity
+        r, c = np.nonzero(f > 0)
+        ctr = 15.5
+        assert np.max(np.hypot(r - ctr, c - ctr)) <= 16.0   # inside the FOV disc
+        assert 0.2 < (f > 0).mean() < 0.7
+    with pytest.raises(ValueError):
+        synth.make_problem(geom, [7], phantom="square")
