@@ -31,6 +31,9 @@ sys.path.insert(0, ROOT)
 METRIC = ("APPGA iters/s at 128²×batch64 vs plain; projector HBM GB/s; "
           "p50/p99 recon latency")
 HBM_PEAK_GBS = 8000.0
+# LDS read rate of 16-byte reads per lane, conflict-free, all CUs: 209 B/clk/CU x 256 CUs x
+# 2.4 GHz, as measured on MI355X (the on-chip bound of the tile projections)
+LDS_PEAK_BPS = 128.4e12
 KERNELS_SRC = os.path.join(ROOT, "paper_2409_13344_amd", "csrc", "kernels.hip")
 
 # HBM traffic per launch from two rocprofv3 passes (FETCH_SIZE, then WRITE_SIZE; KiB per
@@ -270,7 +273,9 @@ def main():
     s_idx = 2 if max(m, d) <= 65536 else 4
     kernels = {}
     tiles = "back_tiles" in times
-    for name, kind in (("forward_batch", "forward"), ("back_tiles", "back"),
+    tinfo = {"fwd_tiles": ap.appga_matrix_tiles(mat, ap.APPGA_TILES_FORWARD),
+             "back_tiles": ap.appga_matrix_tiles(mat, ap.APPGA_TILES_BACK)}
+    for name, kind in (("forward_batch", "forward"), ("fwd_tiles", "forward"), ("back_tiles", "back"),
                        ("step_batch", "update" if tiles else "step")):
         t = times.get(name)
         if not t or t["count"] == 0:
@@ -278,6 +283,15 @@ def main():
         avg_ms = t["total_ms"] / t["count"]
         nbytes = kernel_bytes(kind, nnz, m, d, B, s_val, s_idx)
         kernels[name] = dict(avg_us=1e3 * avg_ms, bytes=nbytes, gbs=nbytes / (avg_ms * 1e-3) / 1e9)
+        if name in tinfo:
+            # on-chip side of a tile kernel: every stored entry (quad padding
+            # included) reads its input's 256-byte record of 64 solves from LDS
+            ti = tinfo[name]
+            lds = ti["entries"] * 256 * (B // 64)
+            kernels[name].update(lds_bytes=lds, lds_tbs=lds / (avg_ms * 1e-3) / 1e12,
+                                 lds_frac=lds / (avg_ms * 1e-3) / LDS_PEAK_BPS,
+                                 staged_records=ti["records"], windows=ti["windows"], tiles=ti["tiles"],
+                                 split=ti["split"])
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
     roof = dict(bound="hbm", achieved=round(kernels[dom]["gbs"], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(kernels[dom]["gbs"] / HBM_PEAK_GBS, 4),
@@ -375,6 +389,7 @@ def main():
         "serving": serving,
         "projector_single_256": projector,
         "matrix_bytes": info,
+        "tile_forms": tinfo,
         "tuning": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tuning.items()},
         "objective_lane0": stats[0]["objective"],
     }

@@ -138,6 +138,30 @@ appga_status appga_free_system_matrix(appga_ctx *ctx, appga_matrix *mat);
 appga_status appga_matrix_info(const appga_matrix *mat, int64_t *nnz, int64_t *bytes_a,
                                int64_t *bytes_at, int32_t *storage);
 
+/* Tile forms of a loaded matrix (Section 2.2: A x and A^T e of batches).  For
+ * B > 1 the library projects over tiles of 64 outputs (rays for A x, 8 x 8
+ * pixel blocks for A^T e) whose entries read their inputs from windows staged
+ * in on-chip memory; appga_load_system_matrix builds them unless
+ * APPGA_FWD_TILES=0 / APPGA_BACK_TILES=0, and falls back to the row kernels
+ * for a direction whose tile form does not fit the kernel's limits.  Results
+ * agree with the row kernels to FP32 rounding (the back projection with one
+ * workgroup per tile, APPGA_BACK_SPLIT=1, bit for bit).  `which` is
+ * APPGA_TILES_FORWARD or APPGA_TILES_BACK; *out receives the tile form's
+ * counts (valid = 0: the row kernels serve that direction).
+ * Errors: APPGA_E_INVALID_ARG (NULL pointer or unknown `which`). */
+enum { APPGA_TILES_FORWARD = 0, APPGA_TILES_BACK = 1 };
+typedef struct {
+    int32_t valid;      /* 1: the tile kernel serves B > 1 in this direction */
+    int32_t tiles;      /* tiles of 64 outputs */
+    int32_t split;      /* workgroups per tile (partial sums; forward: 1) */
+    int32_t pad0;
+    int64_t windows;    /* windows staged over all tiles */
+    int64_t records;    /* input records staged over all windows (256 bytes per 64 solves) */
+    int64_t entries;    /* stored entries including the quad padding */
+    int64_t bytes;      /* device bytes of the tile form */
+} appga_tile_info;
+appga_status appga_matrix_tiles(const appga_matrix *mat, int32_t which, appga_tile_info *out);
+
 /* Launch-configuration autotuner.  Times the candidate launch configurations
  * of the projector kernels for `mat` on the device and keeps the fastest:
  * APPGA_TUNE_SINGLE -- lanes per matrix row (4..64) of the single-solve

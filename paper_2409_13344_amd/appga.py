@@ -100,6 +100,7 @@ _SIGS = {
     "appga_submit": [P, P, P, P, C.POINTER(appga_params), C.POINTER(U64)],
     "appga_wait": [P, U64, P, C.POINTER(appga_stats), I32],
     "appga_server_stop": [P],
+    "appga_matrix_tiles": [P, I32, P],
 }
 
 
@@ -212,6 +213,21 @@ def appga_matrix_info(mat) -> dict:
     nnz, ba, bt, stg = I64(), I64(), I64(), I32()
     _call("appga_matrix_info", mat, C.byref(nnz), C.byref(ba), C.byref(bt), C.byref(stg))
     return dict(nnz=nnz.value, bytes_a=ba.value, bytes_at=bt.value, storage=stg.value)
+
+
+class appga_tile_info(C.Structure):
+    _fields_ = [("valid", I32), ("tiles", I32), ("split", I32), ("pad0", I32), ("windows", I64),
+                ("records", I64), ("entries", I64), ("bytes", I64)]
+
+
+APPGA_TILES_FORWARD, APPGA_TILES_BACK = 0, 1
+
+
+def appga_matrix_tiles(mat, which: int) -> dict:
+    """Counts of the tile form of `mat` for A x (APPGA_TILES_FORWARD) or A^T e (APPGA_TILES_BACK)."""
+    info = appga_tile_info()
+    _call("appga_matrix_tiles", mat, which, C.byref(info))
+    return {k: getattr(info, k) for k, _ in info._fields_ if k != "pad0"}
 
 
 def appga_matrix_dequantized(mat, nnz: int) -> np.ndarray:

@@ -18,7 +18,7 @@
 
 #include "appga_internal.h"
 #include "appga_impl.h"
-#include "back_tiles.h"
+#include "gather_tiles.h"
 
 using namespace appga;
 
@@ -378,27 +378,34 @@ appga_status to_device(const HostPacked &hp, int64_t nrows, int64_t ncols, int64
     return APPGA_OK;
 }
 
-appga_status back_tiles_to_device(const HostBackTiles &h, DevBackTiles &d) {
-    d = DevBackTiles();
+appga_status gather_tiles_to_device(const HostGatherTiles &h, DevGatherTiles &d) {
+    d = DevGatherTiles();
+    d.n_tiles = h.n_tiles;
     d.tiles_x = h.tiles_x;
     d.n_groups = h.n_groups;
     d.group_angles = h.group_angles;
-    d.n_entries = static_cast<int64_t>(h.word.size());
-    d.n_rays = static_cast<int64_t>(h.rays.size());
+    d.max_windows = h.max_windows;
+    d.n_windows = static_cast<int64_t>(h.rec_off.size()) - 1;
+    d.n_records = static_cast<int64_t>(h.records.size());
+    d.n_words = static_cast<int64_t>(h.word.size());
+    ST_TRY(upload(h.win_off, reinterpret_cast<void **>(&d.win_off), d.bytes));
+    ST_TRY(upload(h.rec_off, reinterpret_cast<void **>(&d.rec_off), d.bytes));
+    ST_TRY(upload(h.records, reinterpret_cast<void **>(&d.records), d.bytes));
     ST_TRY(upload(h.rp, reinterpret_cast<void **>(&d.rp), d.bytes));
     ST_TRY(upload(h.word, reinterpret_cast<void **>(&d.word), d.bytes));
-    ST_TRY(upload(h.ray_off, reinterpret_cast<void **>(&d.ray_off), d.bytes));
-    ST_TRY(upload(h.rays, reinterpret_cast<void **>(&d.rays), d.bytes));
+    ST_TRY(upload(h.outs, reinterpret_cast<void **>(&d.outs), d.bytes));
     d.valid = 1;
     return APPGA_OK;
 }
 
-void free_back_tiles(DevBackTiles &d) {
+void free_gather_tiles(DevGatherTiles &d) {
+    hipFree(d.win_off);
+    hipFree(d.rec_off);
+    hipFree(d.records);
     hipFree(d.rp);
     hipFree(d.word);
-    hipFree(d.ray_off);
-    hipFree(d.rays);
-    d = DevBackTiles();
+    hipFree(d.outs);
+    d = DevGatherTiles();
 }
 
 void free_csr(DevCsr &dc) {
@@ -531,22 +538,32 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
         if (st == APPGA_OK) st = to_device(ha, m, d, nnz, vtype, mat->A);
         if (st == APPGA_OK) st = to_device(ht, d, m, nnz, vtype, mat->AT);
     }
-    if (st == APPGA_OK && env_int("APPGA_BACK_TILES", 0)) {
-        // value code of each transpose entry as the stored transpose holds it
-        std::vector<uint32_t> tcode(vtype == VT_F32 ? 0 : nnz);
-        std::vector<float> tv32(vtype == VT_F32 ? nnz : 0);
+    // tile forms for batches (B > 1); without them the row kernels serve
+    if (st == APPGA_OK && env_int("APPGA_BACK_TILES", 1)) {
+        // value of each transpose entry as the stored transpose decodes it
+        std::vector<float> tv32(nnz);
         for (int64_t k = 0; k < nnz; ++k) {
+            const float v = static_cast<float>(tval[k]);
             switch (vtype) {
-                case VT_F32: tv32[k] = static_cast<float>(tval[k]); break;
-                case VT_BF16: tcode[k] = f32_to_bf16(static_cast<float>(tval[k])); break;
-                case VT_F16: tcode[k] = f32_to_f16(static_cast<float>(tval[k])); break;
-                default: tcode[k] = tcodes[k]; break;
+                case VT_F32: tv32[k] = v; break;
+                case VT_BF16: tv32[k] = bf16_to_f32_host(f32_to_bf16(v)); break;
+                case VT_F16: tv32[k] = f16_to_f32_host(f32_to_f16(v)); break;
+                default: tv32[k] = static_cast<float>(e4m3_to_f64(tcodes[k])); break;
             }
         }
-        HostBackTiles hb;
-        if (build_back_tiles(geom->n, geom->n_angles, geom->n_bins, trp.data(), tcol.data(), tcode.data(),
-                             tv32.data(), vtype == VT_F32, hb))
-            st = back_tiles_to_device(hb, mat->bt);
+        HostGatherTiles hb;
+        if (build_back_tiles(geom->n, geom->n_angles, geom->n_bins, trp.data(), tcol.data(), tv32.data(), hb))
+            st = gather_tiles_to_device(hb, mat->bt);
+    }
+    if (st == APPGA_OK && env_int("APPGA_FWD_TILES", 1)) {
+        // value of each entry of A as the stored matrix decodes it (FP8: the
+        // code without its row scale)
+        std::vector<float> v32(nnz);
+        for (int64_t k = 0; k < nnz; ++k)
+            v32[k] = vtype == VT_FP8 ? static_cast<float>(e4m3_to_f64(codes[k])) : static_cast<float>(mat->deq[k]);
+        HostGatherTiles hf;
+        if (build_fwd_tiles(geom->n, geom->n_angles, geom->n_bins, row_ptr, col_idx, v32.data(), hf))
+            st = gather_tiles_to_device(hf, mat->ft);
     }
     if (st == APPGA_OK) {
         // Lambda = A^T 1 of the stored (dequantised) values, zeros -> 1 (eq. EM)
@@ -560,7 +577,8 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
     if (st != APPGA_OK) {
         free_csr(mat->A);
         free_csr(mat->AT);
-        free_back_tiles(mat->bt);
+        free_gather_tiles(mat->bt);
+        free_gather_tiles(mat->ft);
         hipFree(mat->lam);
         delete mat;
         return st;
@@ -582,7 +600,8 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
         if (ts != APPGA_OK) {
             free_csr(mat->A);
             free_csr(mat->AT);
-            free_back_tiles(mat->bt);
+            free_gather_tiles(mat->bt);
+            free_gather_tiles(mat->ft);
             hipFree(mat->lam);
             delete mat;
             return ts;
@@ -601,7 +620,8 @@ extern "C" appga_status appga_free_system_matrix(appga_ctx *ctx, appga_matrix *m
     hipStreamSynchronize(ctx->stream);
     free_csr(mat->A);
     free_csr(mat->AT);
-    free_back_tiles(mat->bt);
+    free_gather_tiles(mat->bt);
+    free_gather_tiles(mat->ft);
     hipFree(mat->lam);
     delete mat;
     return APPGA_OK;
@@ -615,6 +635,23 @@ extern "C" appga_status appga_matrix_info(const appga_matrix *mat, int64_t *nnz,
     if (bytes_a) *bytes_a = mat->A.bytes;
     if (bytes_at) *bytes_at = mat->AT.bytes;
     if (storage) *storage = mat->storage;
+    return APPGA_OK;
+}
+
+extern "C" appga_status appga_matrix_tiles(const appga_matrix *mat, int32_t which, appga_tile_info *out) {
+    clear_error();
+    if (!mat || !out) return fail(APPGA_E_INVALID_ARG, "NULL matrix or output");
+    if (which != APPGA_TILES_FORWARD && which != APPGA_TILES_BACK)
+        return fail(APPGA_E_INVALID_ARG, "which must be APPGA_TILES_FORWARD or APPGA_TILES_BACK");
+    const DevGatherTiles &t = which == APPGA_TILES_FORWARD ? mat->ft : mat->bt;
+    *out = appga_tile_info{};
+    out->valid = t.valid;
+    out->tiles = t.n_tiles;
+    out->split = which == APPGA_TILES_BACK ? mat->bt_split : 1;
+    out->windows = t.n_windows;
+    out->records = t.n_records;
+    out->entries = t.n_words / 2;
+    out->bytes = t.bytes;
     return APPGA_OK;
 }
 
@@ -752,6 +789,11 @@ static appga_status sess_theta(appga_solve *s, int k0) {
 }
 
 // FP64 objective Phi(x) per solve (Section 2.1) into host vector out.
+hipError_t launch_forward_mat(const appga_matrix *mat, const FwdArgs &fa, hipStream_t st) {
+    if (forward_uses_tiles(mat, fa)) return launch_fwd_tiles(mat->ft, mat->A.vtype, fa, st);
+    return launch_forward(mat->A, fa, mat->group_fwd, st);
+}
+
 appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> &out,
                             double *part = nullptr, double *red = nullptr) {
     if (!part) part = s->part;
@@ -776,8 +818,8 @@ appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> 
     fa.gamma_lane = s->gamma_lane;
     fa.out = s->e;
     fa.mode = FM_PROJ;
-    HIP_TRY(timed_launch(s->ctx, "forward_proj", s->st,
-                         [&] { return launch_forward(mat->A, fa, mat->group_fwd, s->st); }));
+    HIP_TRY(timed_launch(s->ctx, forward_uses_tiles(mat, fa) ? "forward_proj_tiles" : "forward_proj", s->st,
+                         [&] { return launch_forward_mat(mat, fa, s->st); }));
     HIP_TRY(launch_fidelity_terms(m, B, s->e, s->g, s->gamma, s->gamma_lane, part, s->st));
     HIP_TRY(launch_reduce_partials(part, fidelity_blocks(m), B, 1, red, s->st));
     HIP_TRY(launch_reg_value(n, B, x, s->lp, part, s->st));
@@ -941,8 +983,8 @@ appga_status sess_step(appga_solve *s, int n_iters) {
         fa.scale_out = 1;
         fa.fwd_wgs = mat->fwd_wgs;
         fa.clamps = s->clamps;
-        HIP_TRY(timed_launch(s->ctx, B == 1 ? "forward_single" : "forward_batch", s->st,
-                             [&] { return launch_forward(mat->A, fa, mat->group_fwd, s->st); }));
+        const char *fname = B == 1 ? "forward_single" : (forward_uses_tiles(mat, fa) ? "fwd_tiles" : "forward_batch");
+        HIP_TRY(timed_launch(s->ctx, fname, s->st, [&] { return launch_forward_mat(mat, fa, s->st); }));
         StepArgs sa{};
         sa.row_ptr = mat->AT.row_ptr;
         sa.col = mat->AT.col;
@@ -1263,8 +1305,8 @@ appga_status op_forward_impl(appga_ctx *ctx, const appga_matrix *mat, int B, con
     fa.mode = mode;
     fa.scale_out = scale_out;
     fa.fwd_wgs = mat->fwd_wgs;
-    HIP_TRY(timed_launch(ctx, B == 1 ? "op_forward_single" : "op_forward_batch", st,
-                         [&] { return launch_forward(mat->A, fa, mat->group_fwd, st); }));
+    const char *fname = B == 1 ? "op_forward_single" : (forward_uses_tiles(mat, fa) ? "op_fwd_tiles" : "op_forward_batch");
+    HIP_TRY(timed_launch(ctx, fname, st, [&] { return launch_forward_mat(mat, fa, st); }));
     ST_TRY(from_internal(y, d_y, B, m, st));
     HIP_TRY(hipStreamSynchronize(st));
     return APPGA_OK;

@@ -32,7 +32,8 @@ struct appga_matrix {
     int64_t nnz = 0;
     int storage = 0;
     appga::DevCsr A, AT;
-    appga::DevBackTiles bt;            // B > 1 back projection over pixel tiles (bt.valid = 0: none)
+    appga::DevGatherTiles bt;          // B > 1 back projection over pixel tiles (bt.valid = 0: none)
+    appga::DevGatherTiles ft;          // B > 1 forward projection over ray tiles (ft.valid = 0: none)
     float *lam = nullptr;              // Lambda (d), device
     std::vector<double> deq;           // dequantised values in the caller's CSR order
     std::vector<int64_t> user_row_ptr; // caller's CSR structure (for reports)
@@ -107,6 +108,14 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
 appga_status sess_step(appga_solve *s, int n_iters);
 appga_status sess_end(appga_solve *s, float *d_out, appga_stats *stats, bool free_session);
 appga_status tune_matrix(appga_ctx *ctx, appga_matrix *mat, int flags, appga_tuning *out);
+
+// Forward projection: over the ray tiles when the matrix has them and the
+// batch fills 64-lane chunks, else the row kernels.  *name (optional)
+// receives the kernel timing name.
+hipError_t launch_forward_mat(const appga_matrix *mat, const appga::FwdArgs &fa, hipStream_t st);
+inline bool forward_uses_tiles(const appga_matrix *mat, const appga::FwdArgs &fa) {
+    return mat->ft.valid && fa.Bp >= 64;
+}
 void sess_free(appga_solve *s);
 
 }  // namespace appga

@@ -36,51 +36,66 @@ struct DevCsr {
     int64_t bytes = 0;           // stored bytes (values + indices + row_ptr + scales)
 };
 
-// Back projection over pixel tiles for B > 1 (built from the transpose at load
-// time).  The image is cut into kBackTile x kBackTile tiles; the angles into
-// groups of `group_angles` consecutive angles (rays i with
-// i / (n_bins * group_angles) == g).  For tile t and group g, the distinct
-// rays that cross the tile, ascending, are the slots of the residual window
-// staged in LDS: rays[ray_off[t*G + g] + s] is the ray in slot s (at most
-// kBackSlots slots).  The entries of tile-local pixel p (row-major within the
-// tile) in group g are entries [rp[(t*G + g)*64 + p], rp[... + 1]) (at most 64),
-// in ray order: word = slot*256 | code << 16 for 16- and 8-bit values (the
-// stored value code); for FP32 values each entry is two words, slot*256 and
-// the value's bits, and the offsets count words.  The lists of the pixel pair
-// (2i, 2i+1) are padded to one common multiple of 4 entries with zero-valued
-// entries whose slot is kBackSlots (a record of zeros the kernel keeps in
-// LDS).  Device pointers.
+// Tile form of a sparse operator for batches (B > 1).  The outputs are cut
+// into tiles of 64; a tile's sums run over windows, each a list of at most
+// kBackSlots input records (records[rec_off[w] + s] is the input in slot s)
+// that the kernel stages in LDS.  For window w the entries of tile slot o are
+// words [rp[w*64 + o], rp[w*64 + o + 1]): pairs (slot * 256, FP32 value),
+// where slot kBackSlots is a record of zeros the kernel keeps in LDS.  The
+// lists of slots 4i .. 4i+3 (a quad) have equal lengths (padded with zero
+// entries).  Tile t owns windows [win_off[t], win_off[t+1]) and its slot o
+// is output outs[t*64 + o] (-1: none).
+//  - Back projection A^T e: tiles of kBackTile x kBackTile pixels (slot =
+//    row-major position in the tile, outputs = pixels r*N + c), windows = the
+//    groups of `group_angles` consecutive angles (records = the rays that
+//    cross the tile), every tile has n_groups windows.
+//  - Forward projection A x: tiles of kFwdTileAngles angles x kFwdTileBins
+//    bins (slot = angle * kFwdTileBins + bin within the tile, outputs = rays),
+//    windows = runs of the pixels the tile's rays cross, ordered along the
+//    tile's mean ray direction (records = pixels).
+// Each output's entries keep their stored order within a window.  Device
+// pointers.
 constexpr int kBackTile = 8;
+constexpr int kFwdTileAngles = 8;
+constexpr int kFwdTileBins = 8;
 constexpr int kBackSlots = 96;       // records per window (slot kBackSlots is the zero record)
-constexpr int kBackMaxGroups = 48;
-constexpr int kBackMaxWords = 2048;  // entries of one tile in one group (padded)
+constexpr int kBackMaxWords = 2048;  // words of one tile in one window (padded)
 
-struct DevBackTiles {
+struct DevGatherTiles {
     int valid = 0;
-    int tiles_x = 0, n_groups = 0, group_angles = 0;
-    uint32_t *rp = nullptr;
-    uint32_t *word = nullptr;
-    uint32_t *ray_off = nullptr;
-    uint32_t *rays = nullptr;
-    int64_t n_entries = 0, n_rays = 0;
+    int n_tiles = 0;
+    int tiles_x = 0;                 // pixel tiles per image row (back projection), else 0
+    int n_groups = 0, group_angles = 0;  // back projection: windows per tile, angles per window
+    int max_windows = 0;             // most windows of one tile
+    uint32_t *win_off = nullptr;     // [n_tiles + 1]
+    uint32_t *rec_off = nullptr;     // [n_windows + 1]
+    uint32_t *records = nullptr;     // [n_records]
+    uint32_t *rp = nullptr;          // [n_windows * 64 + 1]
+    uint32_t *word = nullptr;        // [n_words]
+    int32_t *outs = nullptr;         // [n_tiles * 64]
+    int64_t n_windows = 0, n_records = 0, n_words = 0;
     int64_t bytes = 0;
 };
 
-struct BackTileArgs {
+enum GatherMode { GM_BACK = 0, GM_FWD = 1 };
+
+struct GatherTileArgs {
+    const uint32_t *win_off;
+    const uint32_t *rec_off;
+    const uint32_t *records;
     const uint32_t *rp;
     const uint32_t *word;
-    const uint32_t *ray_off;
-    const uint32_t *rays;
-    uint32_t n_entries;     // length of word
-    uint32_t n_rays;        // length of rays
-    int n;                  // image side
-    int tiles_x;            // tiles per image row
-    int n_groups;
-    int m;                  // rays (length of e per solve)
+    const int32_t *outs;
+    uint32_t n_records;     // length of records
+    uint32_t n_words;       // length of word
+    int n_tiles;
+    int tiles_x;            // > 0: square grid of pixel tiles (the XCD remap applies)
     int xcd_remap;
-    int split;              // workgroups per tile; workgroup s sums groups [s G / split, (s+1) G / split)
-    const float *e;         // [m] lane layout, chunk blockIdx.y
-    float *out;             // [split][d] lane layout: the partial sums of A^T e
+    int split;              // GM_BACK: workgroups per tile; workgroup s sums windows [s W / split, (s+1) W / split)
+    int n_in;               // input records per chunk (rays for A^T e, pixels for A x)
+    int n_out;              // outputs per chunk
+    const float *in;        // [chunk][n_in][64] (lane layout)
+    float *out;             // GM_BACK: [split][chunk][n_out][64] partial sums
 };
 
 // Per-solve (per batch lane) parameters, FP32 copies of the FP64 host values.
@@ -160,13 +175,18 @@ struct StepArgs {
     int xcd_remap;           // 1: map workgroups to spatially compact tile blocks per XCD
 };
 
-// Serving helpers (kernels.hip).
-// B > 1 back projection out = A^T e over the tiles (lane layout, Bp / 64 chunks).
-hipError_t launch_back_tiles(const DevBackTiles &bt, int vtype, int n, int m, int Bp, int xcd_remap,
+// B > 1 back projection out = A^T e over the pixel tiles (lane layout, Bp / 64
+// chunks, `split` partial sums).
+hipError_t launch_back_tiles(const DevGatherTiles &bt, int vtype, int n, int m, int Bp, int xcd_remap,
                              int split, const float *e, float *out, hipStream_t st);
-// Workgroups per tile for the back projection of an n x n image (enough
-// workgroups to put two on every CU).
-int back_tiles_split(const DevBackTiles &bt);
+// Workgroups per tile for the back projection (enough workgroups to put two
+// on every CU).
+int back_tiles_split(const DevGatherTiles &bt);
+// B > 1 forward projection over the ray tiles with the epilogue of `fa`
+// (FM_PROJ or FM_RATIO), fa.Bp / 64 chunks.
+hipError_t launch_fwd_tiles(const DevGatherTiles &ft, int vtype, const FwdArgs &fa, hipStream_t st);
+
+// Serving helpers (kernels.hip).
 
 // Serving: advances the 64 per-lane iteration counters k by one and writes
 // theta_{k+1} (eq. GNtheta, FP64) per lane; mom holds {a, b, omega, momentum_none}.

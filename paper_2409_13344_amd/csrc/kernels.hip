@@ -612,240 +612,253 @@ __global__ __launch_bounds__(1024, 8) void k_step_batch(StepArgs a) {
 }
 
 // ------------------------------------------------------------------------
-// Back projection grad F = A^T e for B > 1 over 8 x 8 pixel tiles (Section 2.2).
+// Projections for B > 1 over tiles (Section 2.2: grad F = A^T e needs A x
+// and A^T e every iteration).
 //
-// Every nonzero of A^T needs the 256-byte lane record of one ray's residual.
-// Gathering those records one by one from L2 is what bounds a row-by-row
-// kernel; here the records a tile needs are staged in LDS and reused.  For a
-// group of consecutive angles only a few rays per angle cross an 8 x 8 tile
-// (about 8 sqrt 2 + 2), so the tile's window for one group is at most
-// kBackSlots records; each is read from L2 once per tile and then serves every
-// entry of the tile's pixels in that group (about 8 on average).  Windows are
-// double buffered: the next group's records are in flight while the current
-// group is summed.  A tile's angle groups are split between `split`
-// workgroups (each writes its own partial sum), so that two workgroups share
-// a CU and one sums while the other waits for its window.  Workgroup = 8
-// waves, lanes = the 64 solves of chunk blockIdx.y; wave w sums the 8 pixels
-// of tile row w; per entry one v_readlane of the packed word (LDS byte offset
-// | value code), one LDS read with the lane as offset and one FMA.  Entries
-// are in the transpose's ray order.
+// A row-by-row kernel gathers, for every stored entry, the 256-byte lane
+// record of its input from L2, and that gather rate is what bounds it.  Here
+// a workgroup owns a tile of 64 outputs and stages in LDS, window after
+// window, the input records its entries refer to; each staged record serves
+// several entries (about 8 for the back projection, whose windows are the
+// rays that cross an 8 x 8 pixel tile at a group of consecutive angles, about
+// 6.6 for the forward projection, whose windows are runs of the pixels that
+// a block of 8 angles x 8 bins of rays crosses).  LDS serves 16-byte reads
+// about 8 times faster than L2 serves such gathers.  Windows are double
+// buffered and their loads issued two windows ahead.  Workgroup = 8 waves,
+// each owning 8 tile slots as two quads of 4; within a wave, 16-lane row q
+// takes slot q of the quad and each of its lanes 4 of the 64 solves of chunk
+// blockIdx.y.  An entry is a pair of words (LDS byte offset of its record,
+// FP32 value).  Each row reads 16 words (8 entries) of its own slot's list
+// with one LDS read per lane, and a DPP row broadcast hands word j to all
+// lanes of the row as an operand.  Per 4 entries (one per slot of the quad):
+// one OR (record addresses), one 16-byte LDS read per lane (the four
+// records), one broadcast of the value and four FMAs.  An output's entries
+// are summed window by window in stored order.  The back projection may split
+// a tile's windows between `split` workgroups (partial sums, added in order
+// by the step kernel) so that two workgroups share a CU.
 // ------------------------------------------------------------------------
 
-template <int VT>
-__device__ __forceinline__ float tile_val(uint32_t word, uint32_t v32) {
-    if constexpr (VT == VT_F32) return __uint_as_float(v32);
-    else if constexpr (VT == VT_BF16) return __uint_as_float(word & 0xFFFF0000u);
-    else if constexpr (VT == VT_F16) return f16_to_f32(word >> 16);
-    else return fp8_to_f32((word >> 16) & 0xFFu);
+// Word J of the calling lane's 16-lane row, in every lane of the row.
+template <int J>
+__device__ __forceinline__ uint32_t row_bcast(uint32_t v) {
+    return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), 0x150 + J, 0xF, 0xF, true));
 }
 
 constexpr int kBackThreads = 512;
-constexpr int kBackPix = 8;         // pixels per wave (one tile row)
+constexpr int kBackPix = 8;         // tile slots per wave
 
-// LDS of the back projection: one array at LDS address 0 (the kernel's only
-// LDS object, 32 KB aligned) so that the second window starts at 32 KB and a
-// record's byte address is (slot * 256) | (window << 15) | (lane << 2): one
-// v_and_or per entry.  Between and after the windows: the ray ids of the next
-// two windows, the tile's word offsets, and two buffers of staged words.
+// LDS of the tile kernel: one array at LDS address 0 (the kernel's only LDS
+// object, 32 KB aligned) so that the second window starts at 32 KB and a
+// record's byte address within a window is (slot * 256) | (lane offset), the
+// window's base being the LDS read's immediate offset.  Between and after the
+// windows: a ring of four windows' word offsets (absolute, 65 per window),
+// two buffers of staged words (16 words of slack after them) and a ring of
+// four windows' record ids.
 constexpr uint32_t kWinBytes = (kBackSlots + 1) * 256;
 constexpr uint32_t kWin1 = 32768;
-constexpr uint32_t kIdsOff = kWinBytes;                                  // u32 [2][kBackSlots]
-constexpr uint32_t kWbOff = kIdsOff + 2 * kBackSlots * 4;                // u32 [kBackMaxGroups + 1]
-constexpr uint32_t kRelOff = kWbOff + (kBackMaxGroups + 1) * 4;          // u16 [kBackMaxGroups][65]
-constexpr uint32_t kWordsOff = kWin1 + kWinBytes;                        // u32 [2][kBackMaxWords]
-constexpr uint32_t kBackLds = kWordsOff + 2 * kBackMaxWords * 4;
-static_assert(kRelOff + kBackMaxGroups * 65 * 2 <= kWin1, "back projection LDS layout");
-static_assert(kBackSlots * 256 <= 0x7F00, "slot offsets must fit bits 8..14");
+constexpr uint32_t kOffsOff = kWinBytes;                                 // u32 [4][65]
+constexpr uint32_t kWordsOff = kWin1 + kWinBytes;                        // u32 [2][kBackMaxWords] + 16
+constexpr uint32_t kIdsOff = kWordsOff + (2 * kBackMaxWords + 16) * 4;   // u32 [4][kBackSlots]
+constexpr uint32_t kBackLds = kIdsOff + 4 * kBackSlots * 4;
+static_assert(kOffsOff + 4 * 65 * 4 <= kWin1, "tile kernel LDS layout");
+static_assert(kBackSlots * 256 + 256 <= kWin1, "a record address is its slot offset OR the lane offset");
 static_assert(kBackMaxWords == 4 * kBackThreads, "one 16-byte word quad per thread");
+static_assert(kBackSlots <= kBackThreads && 65 <= kBackThreads, "one record id and one offset per thread");
 
-template <int VT>
-__global__ __launch_bounds__(kBackThreads) void k_back_tiles(BackTileArgs a) {
+template <int MODE, int VT>
+__global__ __launch_bounds__(kBackThreads) void k_gather_tiles(GatherTileArgs a, FwdArgs f) {
     __shared__ __attribute__((aligned(32768))) uint32_t lds[kBackLds / 4];
     char *const lb = reinterpret_cast<char *>(lds);
     uint32_t *const ids = reinterpret_cast<uint32_t *>(lb + kIdsOff);
-    uint32_t *const wbase = reinterpret_cast<uint32_t *>(lb + kWbOff);
-    uint16_t *const rel = reinterpret_cast<uint16_t *>(lb + kRelOff);
+    uint32_t *const offs = reinterpret_cast<uint32_t *>(lb + kOffsOff);
     uint32_t *const words = reinterpret_cast<uint32_t *>(lb + kWordsOff);
     constexpr int kQ = (kBackSlots * 16 + kBackThreads - 1) / kBackThreads;   // window quads per thread
-    constexpr int kR = (kBackMaxGroups * 65 + kBackThreads - 1) / kBackThreads;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int N = a.n;
-    const int tx = a.tiles_x;
-    const int ntiles = tx * tx;
-    const int part = blockIdx.x / ntiles;
-    const int tile = tile_of(blockIdx.x - part * ntiles, tx, tx, a.xcd_remap);
-    const int r0 = (tile / tx) * kBackTile, c0 = (tile % tx) * kBackTile;
-    const int NG = a.n_groups;
-    const int g0 = part * NG / a.split, g1 = (part + 1) * NG / a.split;
+    const int part = blockIdx.x / a.n_tiles;
+    const int wg = blockIdx.x - part * a.n_tiles;
+    const int tile = a.tiles_x > 0 ? tile_of(wg, a.tiles_x, a.tiles_x, a.xcd_remap) : wg;
     const int chunk = blockIdx.y;
-    const size_t tg0 = static_cast<size_t>(tile) * NG;
+    // this workgroup's windows: [W0, W0 + cnt)
+    const int wt0 = a.win_off[tile], nwt = a.win_off[tile + 1] - wt0;
+    const int i0 = part * nwt / a.split, i1 = (part + 1) * nwt / a.split;
+    const int W0 = wt0 + i0, cnt = i1 - i0;
     // Every global load below is unconditional and range-checked by its buffer
-    // descriptor (out of range reads 0), so the wait counts stay static.
-    const auto er = make_rsrc(reinterpret_cast<const char *>(a.e) + static_cast<size_t>(chunk) * a.m * 256,
-                              256u * static_cast<uint32_t>(a.m));
-    const auto rr = make_rsrc(a.rays, 4u * a.n_rays);
-    const auto wr = make_rsrc(a.word, 4u * a.n_entries);
-    const auto pr = make_rsrc(a.rp + tg0 * 64, 4u * static_cast<uint32_t>(NG * 64 + 1));
+    // descriptor (out of range reads 0); loads for windows past the range fetch
+    // the last window again and are never stored.  So the wait counts are static.
+    const auto er = make_rsrc(reinterpret_cast<const char *>(a.in) + static_cast<size_t>(chunk) * a.n_in * 256,
+                              256u * static_cast<uint32_t>(a.n_in));
+    const auto rr = make_rsrc(a.records, 4u * a.n_records);
+    const auto wr = make_rsrc(a.word, 4u * a.n_words);
+    const auto pr = make_rsrc(a.rp + static_cast<size_t>(W0) * 64, 4u * static_cast<uint32_t>(cnt * 64 + 1));
+    const int jlast = cnt - 1;
 
-    // set-up: zero records, the groups' word offsets (absolute, then relative)
-    if (w == 0) {
-        lds[(kBackSlots * 256) / 4 + lane] = 0u;
-        lds[(kWin1 + kBackSlots * 256) / 4 + lane] = 0u;
-    }
-    if (tid <= NG) wbase[tid] = __builtin_amdgcn_raw_buffer_load_b32(pr, 4u * (64u * tid), 0, 0);
-    {
-        uint32_t v[kR];
-#pragma unroll
-        for (int j = 0; j < kR; ++j) {
-            const uint32_t i = tid + kBackThreads * j, g = i / 65u, p = i % 65u;
-            v[j] = __builtin_amdgcn_raw_buffer_load_b32(pr, 4u * (64u * g + p), 0, 0);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kR; ++j) {
-            const uint32_t i = tid + kBackThreads * j, g = i / 65u;
-            if (g < static_cast<uint32_t>(NG)) rel[i] = static_cast<uint16_t>(v[j] - wbase[g]);
-        }
-    }
+    float4 acc[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
+    const uint32_t k16 = static_cast<uint32_t>(lane & 15) << 4;
+    const uint32_t l16 = static_cast<uint32_t>(lane) & 15u;
+    const int qrow = lane >> 4;
 
-    // ray ids of a group: global -> registers -> LDS, two groups ahead of the sums
-    uint32_t rid = 0u;
-    auto ids_load = [&](int g) {
-        rid = __builtin_amdgcn_raw_buffer_load_b32(rr, 4u * (a.ray_off[tg0 + g] + tid), 0, 0);
-    };
-    auto ids_store = [&](int buf) {
-        if (tid < kBackSlots) ids[buf * kBackSlots + tid] = rid;
-    };
-    // a group's window records (thread tid moves quads tid + kBackThreads j of
-    // 16 per record) and its words (one quad per thread)
-    uint4 stq[kQ], wq;
-    auto stage_load = [&](int g, int buf) {
-#pragma unroll
-        for (int j = 0; j < kQ; ++j) {
-            const uint32_t q = tid + kBackThreads * j, qp = q & 15u;
-            const uint32_t ray = ids[buf * kBackSlots + (q >> 4)];
-            const auto v = __builtin_amdgcn_raw_buffer_load_b128(er, ray * 256u + qp * 16u, 0, 0);
-            stq[j] = make_uint4(v[0], v[1], v[2], v[3]);
+    if (cnt > 0) {
+        if (w == 0) {   // zero records
+            lds[(kBackSlots * 256) / 4 + lane] = 0u;
+            lds[(kWin1 + kBackSlots * 256) / 4 + lane] = 0u;
         }
-        const auto v = __builtin_amdgcn_raw_buffer_load_b128(wr, 4u * (wbase[g] + 4u * tid), 0, 0);
-        wq = make_uint4(v[0], v[1], v[2], v[3]);
-    };
-    auto stage_store = [&](int g, int buf) {
-        const uint32_t S = a.ray_off[tg0 + g + 1] - a.ray_off[tg0 + g];
-        char *const wb = lb + (buf ? kWin1 : 0u);
-#pragma unroll
-        for (int j = 0; j < kQ; ++j) {
-            const uint32_t q = tid + kBackThreads * j, rec = q >> 4, qp = q & 15u;
-            if (rec < S) *reinterpret_cast<uint4 *>(wb + rec * 256 + qp * 16) = stq[j];
-        }
-        if (4u * tid < wbase[g + 1] - wbase[g])
-            *reinterpret_cast<uint4 *>(&words[buf * kBackMaxWords + 4 * tid]) = wq;
-    };
-
-    float acc[kBackPix];
-#pragma unroll
-    for (int p = 0; p < kBackPix; ++p) acc[p] = 0.0f;
-    // sums of group g from window BUF (a compile-time buffer, so that its base
-    // is the LDS read's immediate offset): the words of a pixel pair are read
-    // four entries at a time at one address for the whole wave (an LDS
-    // broadcast); a record's address is (slot * 256) | (lane << 2), assembled by
-    // one v_perm from the word's byte 1 and the lane offset
-    const uint32_t lane4 = static_cast<uint32_t>(lane) << 2;
-    auto compute = [&](int g, auto bufc) {
-        constexpr int BUF = decltype(bufc)::value;
-        const char *const wbase_lds = lb + (BUF ? kWin1 : 0u);
-        const uint32_t *wl = words + BUF * kBackMaxWords;
-        const uint16_t *rg = rel + g * 65 + w * kBackPix;
-        auto xval = [&](uint32_t word) {
-            return *reinterpret_cast<const float *>(wbase_lds + __builtin_amdgcn_perm(word, lane4, 0x0C0C0500u));
+        // record ids and word offsets of window j: global -> registers -> LDS
+        // ring slot j & 3 (ids: threads < kBackSlots, offsets: threads <= 64)
+        auto ids_load = [&](int j) {
+            const int jl = min(j, jlast);
+            return make_uint2(__builtin_amdgcn_raw_buffer_load_b32(rr, 4u * (a.rec_off[W0 + jl] + tid), 0, 0),
+                              __builtin_amdgcn_raw_buffer_load_b32(pr, 4u * (64u * jl + min(tid, 64)), 0, 0));
         };
+        auto ids_store = [&](int j, uint2 v) {
+            if (tid < kBackSlots) ids[(j & 3) * kBackSlots + tid] = v.x;
+            if (tid <= 64) offs[(j & 3) * 65 + tid] = v.y;
+        };
+        // a window's records (thread tid moves quads tid + kBackThreads i of 16
+        // per record) and its words (one quad per thread), in one of two
+        // register sets
+        struct Stage {
+            uint4 q[kQ];
+            uint4 wq;
+        };
+        auto stage_load = [&](int j, Stage &r) {
+            const int jl = min(j, jlast);
+            const uint32_t *idg = ids + (jl & 3) * kBackSlots;
 #pragma unroll
-        for (int p = 0; p < kBackPix; p += 2) {
-            const int s0 = __builtin_amdgcn_readfirstlane(rg[p]);
-            const int s1 = __builtin_amdgcn_readfirstlane(rg[p + 1]);
-            const int n = s1 - s0;       // the pair's lists have equal lengths
-            float u0 = acc[p], u1 = acc[p + 1];
-            if constexpr (VT == VT_F32) {
-                for (int t = 0; t < n; t += 8) {      // (word, value) pairs
-                    const uint4 a0 = *reinterpret_cast<const uint4 *>(wl + s0 + t);
-                    const uint4 a1 = *reinterpret_cast<const uint4 *>(wl + s0 + t + 4);
-                    const uint4 b0 = *reinterpret_cast<const uint4 *>(wl + s1 + t);
-                    const uint4 b1 = *reinterpret_cast<const uint4 *>(wl + s1 + t + 4);
-                    const float xa[4] = {xval(a0.x), xval(a0.z), xval(a1.x), xval(a1.z)};
-                    const float xb[4] = {xval(b0.x), xval(b0.z), xval(b1.x), xval(b1.z)};
-                    u0 = fmaf(__uint_as_float(a0.y), xa[0], u0);
-                    u1 = fmaf(__uint_as_float(b0.y), xb[0], u1);
-                    u0 = fmaf(__uint_as_float(a0.w), xa[1], u0);
-                    u1 = fmaf(__uint_as_float(b0.w), xb[1], u1);
-                    u0 = fmaf(__uint_as_float(a1.y), xa[2], u0);
-                    u1 = fmaf(__uint_as_float(b1.y), xb[2], u1);
-                    u0 = fmaf(__uint_as_float(a1.w), xa[3], u0);
-                    u1 = fmaf(__uint_as_float(b1.w), xb[3], u1);
-                }
-            } else {
-                for (int t = 0; t < n; t += 4) {
-                    const uint4 wa = *reinterpret_cast<const uint4 *>(wl + s0 + t);
-                    const uint4 wb2 = *reinterpret_cast<const uint4 *>(wl + s1 + t);
-                    const float xa[4] = {xval(wa.x), xval(wa.y), xval(wa.z), xval(wa.w)};
-                    const float xb[4] = {xval(wb2.x), xval(wb2.y), xval(wb2.z), xval(wb2.w)};
-                    u0 = fmaf(tile_val<VT>(wa.x, 0u), xa[0], u0);
-                    u1 = fmaf(tile_val<VT>(wb2.x, 0u), xb[0], u1);
-                    u0 = fmaf(tile_val<VT>(wa.y, 0u), xa[1], u0);
-                    u1 = fmaf(tile_val<VT>(wb2.y, 0u), xb[1], u1);
-                    u0 = fmaf(tile_val<VT>(wa.z, 0u), xa[2], u0);
-                    u1 = fmaf(tile_val<VT>(wb2.z, 0u), xb[2], u1);
-                    u0 = fmaf(tile_val<VT>(wa.w, 0u), xa[3], u0);
-                    u1 = fmaf(tile_val<VT>(wb2.w, 0u), xb[3], u1);
-                }
+            for (int i = 0; i < kQ; ++i) {
+                const uint32_t q = tid + kBackThreads * i, qp = q & 15u;
+                const uint32_t rec = idg[min(q >> 4, static_cast<uint32_t>(kBackSlots - 1))];
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(er, rec * 256u + qp * 16u, 0, 0);
+                r.q[i] = make_uint4(v[0], v[1], v[2], v[3]);
             }
-            acc[p] = u0;
-            acc[p + 1] = u1;
-        }
-    };
-
-    // Buffers alternate with the group's position in the workgroup's range
-    // (group g0 + i uses buffer i & 1).  Group g is summed while group g + 1's
-    // records and words and group g + 2's ray ids are in flight.
-    auto iter = [&](int g, auto bufc) {
-        constexpr int BUF = decltype(bufc)::value;
-        const bool more = g + 1 < g1;
-        const bool more2 = g + 2 < g1;
-        if (more) {
-            stage_load(g + 1, BUF ^ 1);
-            if (more2) ids_load(g + 2);
-        }
-        compute(g, bufc);
-        if (more) stage_store(g + 1, BUF ^ 1);
-        if (more2) ids_store(BUF);
-        // all loads of this iteration have landed (the buffer stores waited for them)
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        __syncthreads();
-    };
-    if (g0 < g1) {
-        ids_load(g0);
-        ids_store(0);
-        if (g0 + 1 < g1) {
-            ids_load(g0 + 1);
-            ids_store(1);
-        }
-        __syncthreads();
-        stage_load(g0, 0);
-        stage_store(g0, 0);
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        __syncthreads();
-    }
-    for (int g = g0; g < g1; g += 2) {
-        iter(g, std::integral_constant<int, 0>{});
-        if (g + 1 < g1) iter(g + 1, std::integral_constant<int, 1>{});
-    }
-    const int rr0 = r0 + w;
-    float *out = a.out + (static_cast<size_t>(part) * gridDim.y + chunk) * N * N * 64;
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(wr, 4u * (offs[(jl & 3) * 65] + 4u * tid), 0, 0);
+            r.wq = make_uint4(v[0], v[1], v[2], v[3]);
+        };
+        auto stage_store = [&](int j, int buf, const Stage &r) {
+            const uint32_t S = a.rec_off[W0 + j + 1] - a.rec_off[W0 + j];
+            char *const wb = lb + (buf ? kWin1 : 0u);
 #pragma unroll
-    for (int p = 0; p < kBackPix; ++p) {
-        const int cc = c0 + p;
-        if (rr0 < N && cc < N) out[(static_cast<size_t>(rr0) * N + cc) * 64 + lane] = acc[p];
+            for (int i = 0; i < kQ; ++i) {
+                const uint32_t q = tid + kBackThreads * i, rec = q >> 4, qp = q & 15u;
+                if (rec < S) *reinterpret_cast<uint4 *>(wb + rec * 256 + qp * 16) = r.q[i];
+            }
+            const uint32_t *oj = offs + (j & 3) * 65;
+            if (4u * tid < oj[64] - oj[0]) *reinterpret_cast<uint4 *>(&words[buf * kBackMaxWords + 4 * tid]) = r.wq;
+        };
+
+        // sums of window j from buffer BUF (a compile-time buffer, so that its
+        // base is the LDS read's immediate offset).  The four lists of a quad
+        // have equal lengths; they are summed in blocks of 8 entries and a tail
+        // of 1-7.  Reading 16 words may run past a list's end into the next
+        // list or the slack after the buffers; such words are never used.
+        auto compute = [&](int j, auto bufc) {
+            constexpr int BUF = decltype(bufc)::value;
+            const char *const wbase_lds = lb + (BUF ? kWin1 : 0u);
+            const uint32_t *wl = words + BUF * kBackMaxWords;
+            const uint32_t *oj = offs + (j & 3) * 65;
+            const uint32_t ob = oj[0];
+            const uint32_t *rg = oj + w * kBackPix;
+            // R entries of each list from the row's words q: the record reads
+            // are all issued before the FMAs (a scheduling barrier keeps the
+            // compiler from sinking each read to its FMA)
+            auto block = [&](auto rc, uint32_t q, float4 &u) {
+                constexpr int R = decltype(rc)::value;
+                float4 x[R];
+                [&]<int... J>(std::integer_sequence<int, J...>) {
+                    ((x[J] = *reinterpret_cast<const float4 *>(wbase_lds + (row_bcast<2 * J>(q) | k16))), ...);
+                    __builtin_amdgcn_sched_barrier(0);
+                    auto fma4 = [&](float v, const float4 &xj) {
+                        u.x = fmaf(v, xj.x, u.x);
+                        u.y = fmaf(v, xj.y, u.y);
+                        u.z = fmaf(v, xj.z, u.z);
+                        u.w = fmaf(v, xj.w, u.w);
+                    };
+                    (fma4(__uint_as_float(row_bcast<2 * J + 1>(q)), x[J]), ...);
+                }(std::make_integer_sequence<int, R>{});
+            };
+#pragma unroll
+            for (int qd = 0; qd < 2; ++qd) {
+                const int s0 = __builtin_amdgcn_readfirstlane(rg[4 * qd]);
+                const int s1 = __builtin_amdgcn_readfirstlane(rg[4 * qd + 1]);
+                const int n = (s1 - s0) >> 1;                              // entries of each list
+                const uint32_t *wq = wl + (rg[4 * qd + qrow] - ob) + l16;   // this row's list
+                float4 u = acc[qd];
+                int t = 0;
+                for (; t + 8 <= n; t += 8) block(std::integral_constant<int, 8>{}, wq[2 * t], u);
+                if (t < n) {
+                    const uint32_t q = wq[2 * t];
+                    switch (n - t) {
+                        case 1: block(std::integral_constant<int, 1>{}, q, u); break;
+                        case 2: block(std::integral_constant<int, 2>{}, q, u); break;
+                        case 3: block(std::integral_constant<int, 3>{}, q, u); break;
+                        case 4: block(std::integral_constant<int, 4>{}, q, u); break;
+                        case 5: block(std::integral_constant<int, 5>{}, q, u); break;
+                        case 6: block(std::integral_constant<int, 6>{}, q, u); break;
+                        default: block(std::integral_constant<int, 7>{}, q, u); break;
+                    }
+                }
+                acc[qd] = u;
+            }
+        };
+
+        // Software pipeline over the windows j: window j uses buffer j & 1 and
+        // register set j & 1.  At the start of step j (after a barrier) buffer
+        // j & 1 holds window j, register set (j + 1) & 1 holds window j + 1's
+        // loads (issued one step earlier) and the rings hold windows j .. j + 2.
+        // Step j issues window j + 3's ids and offsets and window j + 2's loads,
+        // sums window j, stores window j + 1 into the other buffer and window
+        // j + 3's ids and offsets into the rings (the slot of window j - 1, last
+        // read in step j - 1), then waits at the barrier: a load has two steps'
+        // sums to land in.
+        Stage rs0, rs1;
+        auto step = [&](int j, auto pc) {
+            constexpr int P = decltype(pc)::value;
+            Stage &mine = P ? rs1 : rs0;
+            Stage &next = P ? rs0 : rs1;
+            const uint2 rid = ids_load(j + 3);
+            stage_load(j + 2, mine);
+            compute(j, std::integral_constant<int, P>{});
+            if (j + 1 < cnt) stage_store(j + 1, P ^ 1, next);
+            if (j + 3 < cnt) ids_store(j + 3, rid);
+            __syncthreads();
+        };
+        {
+            const uint2 r0 = ids_load(0), r1 = ids_load(1), r2 = ids_load(2);
+            ids_store(0, r0);
+            ids_store(1, r1);
+            if (2 < cnt) ids_store(2, r2);
+            __syncthreads();
+            stage_load(0, rs0);
+            stage_load(1, rs1);
+            stage_store(0, 0, rs0);
+            __syncthreads();
+        }
+        for (int j = 0; j < cnt; j += 2) {
+            step(j, std::integral_constant<int, 0>{});
+            if (j + 1 < cnt) step(j + 1, std::integral_constant<int, 1>{});
+        }
+    }
+
+#pragma unroll
+    for (int qd = 0; qd < 2; ++qd) {
+        const int idx = a.outs[tile * 64 + w * kBackPix + 4 * qd + qrow];
+        if (idx < 0) continue;
+        const int bl = 4 * (lane & 15);
+        if constexpr (MODE == GM_BACK) {
+            float *out = a.out + (static_cast<size_t>(part) * gridDim.y + chunk) * a.n_out * 64;
+            *reinterpret_cast<float4 *>(out + static_cast<size_t>(idx) * 64 + bl) = acc[qd];
+        } else {
+            const float v[4] = {acc[qd].x, acc[qd].y, acc[qd].z, acc[qd].w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int b = chunk * 64 + bl + c;
+                const size_t o = (static_cast<size_t>(chunk) * f.m + idx) * 64 + bl + c;
+                const float gl = f.gamma_lane ? f.gamma_lane[b] : 0.0f;
+                const float gam = f.gamma ? f.gamma[o] : gl;
+                fwd_epilogue<VT>(f, idx, b, o, v[c], gam, b < f.B);
+            }
+        }
     }
 }
 
@@ -1237,38 +1250,57 @@ hipError_t launch_scale_rows(float *e, const float *scale, int m, int B, hipStre
     return hipGetLastError();
 }
 
-int back_tiles_split(const DevBackTiles &bt) {
-    const int ntiles = bt.tiles_x * bt.tiles_x;
-    return (ntiles < 512 && bt.n_groups >= 2) ? 2 : 1;
+int back_tiles_split(const DevGatherTiles &bt) {
+    return (bt.n_tiles < 512 && bt.n_groups >= 2) ? 2 : 1;
 }
 
-hipError_t launch_back_tiles(const DevBackTiles &bt, int vtype, int n, int m, int Bp, int xcd_remap,
+static GatherTileArgs gather_args(const DevGatherTiles &t) {
+    GatherTileArgs a{};
+    a.win_off = t.win_off;
+    a.rec_off = t.rec_off;
+    a.records = t.records;
+    a.rp = t.rp;
+    a.word = t.word;
+    a.outs = t.outs;
+    a.n_records = static_cast<uint32_t>(t.n_records);
+    a.n_words = static_cast<uint32_t>(t.n_words);
+    a.n_tiles = t.n_tiles;
+    a.tiles_x = t.tiles_x;
+    return a;
+}
+
+hipError_t launch_back_tiles(const DevGatherTiles &bt, int vtype, int n, int m, int Bp, int xcd_remap,
                              int split, const float *e, float *out, hipStream_t st) {
-    if (!bt.valid || Bp < 64 || Bp % 64 != 0 || split < 1 || split > bt.n_groups) return hipErrorInvalidValue;
-    BackTileArgs a{};
-    a.rp = bt.rp;
-    a.word = bt.word;
-    a.ray_off = bt.ray_off;
-    a.rays = bt.rays;
-    a.n_entries = static_cast<uint32_t>(bt.n_entries);
-    a.n_rays = static_cast<uint32_t>(bt.n_rays);
-    a.n = n;
-    a.tiles_x = bt.tiles_x;
-    a.n_groups = bt.n_groups;
-    a.m = m;
+    (void)vtype;
+    if (!bt.valid || Bp < 64 || Bp % 64 != 0 || split < 1 || split > std::max(1, bt.n_groups))
+        return hipErrorInvalidValue;
+    GatherTileArgs a = gather_args(bt);
     a.xcd_remap = xcd_remap;
     a.split = split;
-    a.e = e;
+    a.n_in = m;
+    a.n_out = n * n;
+    a.in = e;
     a.out = out;
-    const dim3 grid(static_cast<unsigned>(bt.tiles_x * bt.tiles_x * split), static_cast<unsigned>(Bp / 64));
-    const dim3 blk(kBackThreads);
-    switch (vtype) {
-        case VT_F32: hipLaunchKernelGGL(k_back_tiles<VT_F32>, grid, blk, 0, st, a); break;
-        case VT_BF16: hipLaunchKernelGGL(k_back_tiles<VT_BF16>, grid, blk, 0, st, a); break;
-        case VT_F16: hipLaunchKernelGGL(k_back_tiles<VT_F16>, grid, blk, 0, st, a); break;
-        case VT_FP8: hipLaunchKernelGGL(k_back_tiles<VT_FP8>, grid, blk, 0, st, a); break;
-        default: return hipErrorInvalidValue;
-    }
+    const FwdArgs f{};
+    const dim3 grid(static_cast<unsigned>(bt.n_tiles * split), static_cast<unsigned>(Bp / 64));
+    hipLaunchKernelGGL((k_gather_tiles<GM_BACK, VT_F32>), grid, dim3(kBackThreads), 0, st, a, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_tiles(const DevGatherTiles &ft, int vtype, const FwdArgs &fa, hipStream_t st) {
+    if (!ft.valid || fa.Bp < 64 || fa.Bp % 64 != 0) return hipErrorInvalidValue;
+    GatherTileArgs a = gather_args(ft);
+    a.xcd_remap = 0;
+    a.split = 1;
+    a.n_in = fa.n_x;
+    a.n_out = fa.m;
+    a.in = fa.x;
+    a.out = nullptr;
+    const dim3 grid(static_cast<unsigned>(ft.n_tiles), static_cast<unsigned>(fa.Bp / 64));
+    if (vtype == VT_FP8)
+        hipLaunchKernelGGL((k_gather_tiles<GM_FWD, VT_FP8>), grid, dim3(kBackThreads), 0, st, a, fa);
+    else
+        hipLaunchKernelGGL((k_gather_tiles<GM_FWD, VT_F32>), grid, dim3(kBackThreads), 0, st, a, fa);
     return hipGetLastError();
 }
 

@@ -223,7 +223,7 @@ hipError_t enqueue_step(Pool *p, int cur) {
     sa.gf_in = p->gf;
     sa.gf_split = mat->bt_split;
     hipError_t e1 = launch_lane_theta(p->lane_k, p->mom, p->theta, p->stream);
-    if (e1 == hipSuccess) e1 = launch_forward(mat->A, fa, mat->group_fwd, p->stream);
+    if (e1 == hipSuccess) e1 = launch_forward_mat(mat, fa, p->stream);
     if (e1 == hipSuccess && p->gf)
         e1 = launch_back_tiles(mat->bt, mat->AT.vtype, mat->geom.n, mat->A.n_rows, kLanes, mat->bt_remap,
                                mat->bt_split, p->e, p->gf, p->stream);
