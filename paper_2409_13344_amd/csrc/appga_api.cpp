@@ -394,6 +394,11 @@ appga_status gather_tiles_to_device(const HostGatherTiles &h, DevGatherTiles &d)
     ST_TRY(upload(h.rp, reinterpret_cast<void **>(&d.rp), d.bytes));
     ST_TRY(upload(h.word, reinterpret_cast<void **>(&d.word), d.bytes));
     ST_TRY(upload(h.outs, reinterpret_cast<void **>(&d.outs), d.bytes));
+    ST_TRY(upload(h.parts, reinterpret_cast<void **>(&d.parts), d.bytes));
+    ST_TRY(upload(h.reds, reinterpret_cast<void **>(&d.reds), d.bytes));
+    d.n_parts = static_cast<int>(h.parts.size() / 4);
+    d.n_reds = static_cast<int>(h.reds.size() / 4);
+    d.n_pslots = h.n_pslots;
     d.valid = 1;
     return APPGA_OK;
 }
@@ -405,6 +410,8 @@ void free_gather_tiles(DevGatherTiles &d) {
     hipFree(d.rp);
     hipFree(d.word);
     hipFree(d.outs);
+    hipFree(d.parts);
+    hipFree(d.reds);
     d = DevGatherTiles();
 }
 
@@ -562,7 +569,8 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
         for (int64_t k = 0; k < nnz; ++k)
             v32[k] = vtype == VT_FP8 ? static_cast<float>(e4m3_to_f64(codes[k])) : static_cast<float>(mat->deq[k]);
         HostGatherTiles hf;
-        if (build_fwd_tiles(geom->n, geom->n_angles, geom->n_bins, row_ptr, col_idx, v32.data(), hf))
+        if (build_fwd_tiles(geom->n, geom->n_angles, geom->n_bins, row_ptr, col_idx, v32.data(), hf,
+                            env_int("APPGA_FWD_PART_WINDOWS", 0)))
             st = gather_tiles_to_device(hf, mat->ft);
     }
     if (st == APPGA_OK) {
@@ -742,6 +750,8 @@ static appga_status sess_alloc(appga_solve *s) {
     const size_t o_pb = s->need_pbuf ? take(sizeof(float) * d * Bp) : 0;
     const bool tiles = B > 1 && s->mat->bt.valid;
     const size_t o_gf = tiles ? take(sizeof(float) * d * Bp * s->mat->bt_split) : 0;
+    const size_t n_tp = B > 1 && s->mat->ft.valid ? fwd_tile_part_floats(s->mat->ft, Bp) : 0;
+    const size_t o_tp = n_tp ? take(sizeof(float) * n_tp) : 0;
     const size_t o_lp = take(sizeof(LaneParams) * Bp);
     s->theta_cap = 1024;
     const size_t o_th = take(sizeof(float) * (s->theta_cap + 2) * Bp);
@@ -763,6 +773,7 @@ static appga_status sess_alloc(appga_solve *s) {
     s->e = reinterpret_cast<float *>(base + o_e);
     s->pbuf = s->need_pbuf ? reinterpret_cast<float *>(base + o_pb) : nullptr;
     s->gf = tiles ? reinterpret_cast<float *>(base + o_gf) : nullptr;
+    s->tile_part = n_tp ? reinterpret_cast<float *>(base + o_tp) : nullptr;
     s->lp = reinterpret_cast<LaneParams *>(base + o_lp);
     s->theta = reinterpret_cast<float *>(base + o_th);
     s->part = reinterpret_cast<double *>(base + o_part);
@@ -818,6 +829,7 @@ appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> 
     fa.gamma_lane = s->gamma_lane;
     fa.out = s->e;
     fa.mode = FM_PROJ;
+    fa.tile_part = s->tile_part;
     HIP_TRY(timed_launch(s->ctx, forward_uses_tiles(mat, fa) ? "forward_proj_tiles" : "forward_proj", s->st,
                          [&] { return launch_forward_mat(mat, fa, s->st); }));
     HIP_TRY(launch_fidelity_terms(m, B, s->e, s->g, s->gamma, s->gamma_lane, part, s->st));
@@ -983,6 +995,7 @@ appga_status sess_step(appga_solve *s, int n_iters) {
         fa.scale_out = 1;
         fa.fwd_wgs = mat->fwd_wgs;
         fa.clamps = s->clamps;
+        fa.tile_part = s->tile_part;
         const char *fname = B == 1 ? "forward_single" : (forward_uses_tiles(mat, fa) ? "fwd_tiles" : "forward_batch");
         HIP_TRY(timed_launch(s->ctx, fname, s->st, [&] { return launch_forward_mat(mat, fa, s->st); }));
         StepArgs sa{};
@@ -1280,9 +1293,11 @@ appga_status op_forward_impl(appga_ctx *ctx, const appga_matrix *mat, int B, con
     const int64_t m = mat->A.n_rows, d = mat->A.n_cols;
     const int Bp = pad_lanes(B);
     OpBufs ob;
-    const size_t nf = static_cast<size_t>(d) * Bp + 3 * static_cast<size_t>(m) * Bp;
+    const size_t ntp = B > 1 && mat->ft.valid ? fwd_tile_part_floats(mat->ft, Bp) : 0;
+    const size_t nf = static_cast<size_t>(d) * Bp + 3 * static_cast<size_t>(m) * Bp + ntp;
     HIP_TRY(hipMalloc(&ob.mem, sizeof(float) * nf));
     float *x = static_cast<float *>(ob.mem), *g = x + d * Bp, *gam = g + m * Bp, *y = gam + m * Bp;
+    float *tp = ntp ? y + m * Bp : nullptr;
     ST_TRY(to_internal(d_x, x, B, d, st));
     if (d_g) ST_TRY(to_internal(d_g, g, B, m, st));
     if (d_gamma) ST_TRY(to_internal(d_gamma, gam, B, m, st));
@@ -1305,6 +1320,7 @@ appga_status op_forward_impl(appga_ctx *ctx, const appga_matrix *mat, int B, con
     fa.mode = mode;
     fa.scale_out = scale_out;
     fa.fwd_wgs = mat->fwd_wgs;
+    fa.tile_part = tp;
     const char *fname = B == 1 ? "op_forward_single" : (forward_uses_tiles(mat, fa) ? "op_fwd_tiles" : "op_forward_batch");
     HIP_TRY(timed_launch(ctx, fname, st, [&] { return launch_forward_mat(mat, fa, st); }));
     ST_TRY(from_internal(y, d_y, B, m, st));

@@ -60,6 +60,7 @@ struct appga_solve {
     float *g = nullptr, *gamma = nullptr, *gamma_lane = nullptr, *f = nullptr, *ft[2] = {nullptr, nullptr},
           *e = nullptr, *pbuf = nullptr, *theta = nullptr;
     float *gf = nullptr;   // A^T e from the tile kernel (B > 1 with tiles), else null
+    float *tile_part = nullptr;  // partial sums of split forward tiles (B > 1), else null
     appga::LaneParams *lp = nullptr;
     double *part = nullptr, *red = nullptr, *tmc = nullptr;
     unsigned long long *clamps = nullptr;

@@ -58,6 +58,7 @@ struct DevCsr {
 constexpr int kBackTile = 8;
 constexpr int kFwdTileAngles = 8;
 constexpr int kFwdTileBins = 8;
+constexpr int kFwdSlots = 512;       // tile workgroups resident at once (two per CU on 256 CUs)
 constexpr int kBackSlots = 96;       // records per window (slot kBackSlots is the zero record)
 constexpr int kBackMaxWords = 2048;  // words of one tile in one window (padded)
 
@@ -73,9 +74,17 @@ struct DevGatherTiles {
     uint32_t *rp = nullptr;          // [n_windows * 64 + 1]
     uint32_t *word = nullptr;        // [n_words]
     int32_t *outs = nullptr;         // [n_tiles * 64]
+    // forward: the workgroups' parts {tile, first window, end window, partial
+    // slot or kNoSlot}; a tile whose windows are split between several parts
+    // gets one partial-sum slot per part (consecutive), and reds lists those
+    // tiles {tile, first slot, parts, 0} for the reduction that finishes them
+    uint4 *parts = nullptr;
+    uint4 *reds = nullptr;
+    int n_parts = 0, n_reds = 0, n_pslots = 0;
     int64_t n_windows = 0, n_records = 0, n_words = 0;
     int64_t bytes = 0;
 };
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 
 enum GatherMode { GM_BACK = 0, GM_FWD = 1 };
 
@@ -96,6 +105,9 @@ struct GatherTileArgs {
     int n_out;              // outputs per chunk
     const float *in;        // [chunk][n_in][64] (lane layout)
     float *out;             // GM_BACK: [split][chunk][n_out][64] partial sums
+    const uint4 *parts;     // GM_FWD: workgroup parts (then blockIdx.x is a part), or null
+    const uint4 *reds;      // GM_FWD: tiles finished by the reduction
+    int n_pslots;           // GM_FWD: partial-sum slots (64 x 64 values per chunk each)
 };
 
 // Per-solve (per batch lane) parameters, FP32 copies of the FP64 host values.
@@ -144,6 +156,7 @@ struct FwdArgs {
     int scale_out;          // FM_RATIO with FP8: write row_scale[i] * e_i (the transpose has no scales)
     int fwd_wgs;            // B > 1: workgroups of the row-strided grid (0 = default)
     unsigned long long *clamps;  // floored-bin counter (may be null)
+    float *tile_part;       // forward tiles with split tiles: [chunks][n_pslots][64][64] scratch
 };
 
 struct StepArgs {
@@ -183,8 +196,12 @@ hipError_t launch_back_tiles(const DevGatherTiles &bt, int vtype, int n, int m, 
 // on every CU).
 int back_tiles_split(const DevGatherTiles &bt);
 // B > 1 forward projection over the ray tiles with the epilogue of `fa`
-// (FM_PROJ or FM_RATIO), fa.Bp / 64 chunks.
+// (FM_PROJ or FM_RATIO), fa.Bp / 64 chunks; fa.tile_part must hold
+// fwd_tile_part_floats(ft, fa.Bp) floats when the tile form splits tiles.
 hipError_t launch_fwd_tiles(const DevGatherTiles &ft, int vtype, const FwdArgs &fa, hipStream_t st);
+inline size_t fwd_tile_part_floats(const DevGatherTiles &ft, int Bp) {
+    return static_cast<size_t>(ft.n_pslots) * 64 * static_cast<size_t>(Bp);
+}
 
 // Serving helpers (kernels.hip).
 

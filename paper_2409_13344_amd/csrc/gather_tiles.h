@@ -7,6 +7,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <numeric>
 #include <cstdint>
 #include <vector>
@@ -17,9 +18,10 @@ namespace appga {
 
 // Host copy of a DevGatherTiles.
 struct HostGatherTiles {
-    int n_tiles = 0, tiles_x = 0, n_groups = 0, group_angles = 0, max_windows = 0;
+    int n_tiles = 0, tiles_x = 0, n_groups = 0, group_angles = 0, max_windows = 0, n_pslots = 0;
     std::vector<uint32_t> win_off, rec_off, records, rp, word;
     std::vector<int32_t> outs;
+    std::vector<uint32_t> parts, reds;   // 4 words each (DevGatherTiles::parts / reds)
 };
 
 // Tile form of the transpose for the B > 1 back projection:
@@ -205,7 +207,7 @@ inline bool build_back_tiles(int n, int n_angles, int n_bins, const int64_t *trp
 // the epilogue applies).  Returns false when a tile fits no window size within
 // the kernel's limits.
 inline bool build_fwd_tiles(int n, int n_angles, int n_bins, const int64_t *row_ptr, const int32_t *col,
-                            const float *v32, HostGatherTiles &ft) {
+                            const float *v32, HostGatherTiles &ft, int64_t part_windows = -1) {
     const int TA = kFwdTileAngles, TB = kFwdTileBins;
     static_assert(kFwdTileAngles * kFwdTileBins == 64, "64 slots per tile");
     const int64_t d = static_cast<int64_t>(n) * n;
@@ -349,6 +351,27 @@ inline bool build_fwd_tiles(int n, int n_angles, int n_bins, const int64_t *row_
     }
     ft.win_off[ntiles] = static_cast<uint32_t>(ft.rec_off.size() - 1);
     ft.rp.push_back(static_cast<uint32_t>(ft.word.size()));
+    // Workgroup parts: one workgroup sums a tile unless the tile has more than
+    // K windows; then its windows are split into near-equal runs (partial sums
+    // added by a reduction).  part_windows < 0: K about the mean windows per
+    // workgroup slot of the device (two per CU); 0: no splitting; else K.
+    const int64_t nwin = static_cast<int64_t>(ft.rec_off.size()) - 1;
+    const int64_t K = part_windows < 0 ? std::max<int64_t>(4, (nwin + kFwdSlots - 1) / kFwdSlots + 1)
+                      : part_windows == 0 ? std::numeric_limits<int64_t>::max() : part_windows;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const int64_t w0 = ft.win_off[t], nw = ft.win_off[t + 1] - w0;
+        const int64_t np = std::max<int64_t>(1, (nw + K - 1) / K);
+        if (np > 1) {
+            ft.reds.insert(ft.reds.end(), {static_cast<uint32_t>(t), static_cast<uint32_t>(ft.n_pslots),
+                                           static_cast<uint32_t>(np), 0u});
+        }
+        for (int64_t p = 0; p < np; ++p) {
+            const uint32_t slot = np > 1 ? static_cast<uint32_t>(ft.n_pslots + p) : kNoSlot;
+            ft.parts.insert(ft.parts.end(), {static_cast<uint32_t>(t), static_cast<uint32_t>(w0 + p * nw / np),
+                                             static_cast<uint32_t>(w0 + (p + 1) * nw / np), slot});
+        }
+        if (np > 1) ft.n_pslots += static_cast<int>(np);
+    }
     return ft.word.size() < (1ull << 31);
 }
 

@@ -676,14 +676,27 @@ __global__ __launch_bounds__(kBackThreads) void k_gather_tiles(GatherTileArgs a,
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int part = blockIdx.x / a.n_tiles;
-    const int wg = blockIdx.x - part * a.n_tiles;
-    const int tile = a.tiles_x > 0 ? tile_of(wg, a.tiles_x, a.tiles_x, a.xcd_remap) : wg;
     const int chunk = blockIdx.y;
-    // this workgroup's windows: [W0, W0 + cnt)
-    const int wt0 = a.win_off[tile], nwt = a.win_off[tile + 1] - wt0;
-    const int i0 = part * nwt / a.split, i1 = (part + 1) * nwt / a.split;
-    const int W0 = wt0 + i0, cnt = i1 - i0;
+    // this workgroup's tile and windows [W0, W0 + cnt): a listed part, or part
+    // `part` of `split` equal runs of its tile's windows
+    int part, tile, W0, cnt;
+    uint32_t pslot = kNoSlot;
+    if (a.parts) {
+        const uint4 pd = a.parts[blockIdx.x];
+        part = 0;
+        tile = static_cast<int>(pd.x);
+        W0 = static_cast<int>(pd.y);
+        cnt = static_cast<int>(pd.z - pd.y);
+        pslot = pd.w;
+    } else {
+        part = blockIdx.x / a.n_tiles;
+        const int wg = blockIdx.x - part * a.n_tiles;
+        tile = a.tiles_x > 0 ? tile_of(wg, a.tiles_x, a.tiles_x, a.xcd_remap) : wg;
+        const int wt0 = a.win_off[tile], nwt = a.win_off[tile + 1] - wt0;
+        const int i0 = part * nwt / a.split, i1 = (part + 1) * nwt / a.split;
+        W0 = wt0 + i0;
+        cnt = i1 - i0;
+    }
     // Every global load below is unconditional and range-checked by its buffer
     // descriptor (out of range reads 0); loads for windows past the range fetch
     // the last window again and are never stored.  So the wait counts are static.
@@ -848,6 +861,10 @@ __global__ __launch_bounds__(kBackThreads) void k_gather_tiles(GatherTileArgs a,
         if constexpr (MODE == GM_BACK) {
             float *out = a.out + (static_cast<size_t>(part) * gridDim.y + chunk) * a.n_out * 64;
             *reinterpret_cast<float4 *>(out + static_cast<size_t>(idx) * 64 + bl) = acc[qd];
+        } else if (pslot != kNoSlot) {   // a part of a split tile: partial sums
+            const int o = w * kBackPix + 4 * qd + qrow;
+            float *pp = f.tile_part + ((static_cast<size_t>(chunk) * a.n_pslots + pslot) * 64 + o) * 64;
+            *reinterpret_cast<float4 *>(pp + bl) = acc[qd];
         } else {
             const float v[4] = {acc[qd].x, acc[qd].y, acc[qd].z, acc[qd].w};
 #pragma unroll
@@ -858,6 +875,45 @@ __global__ __launch_bounds__(kBackThreads) void k_gather_tiles(GatherTileArgs a,
                 const float gam = f.gamma ? f.gamma[o] : gl;
                 fwd_epilogue<VT>(f, idx, b, o, v[c], gam, b < f.B);
             }
+        }
+    }
+}
+
+// Forward projection, tiles split between parts: the sum of the parts'
+// partial sums in part order, then the epilogue.  Workgroup = one tile of
+// chunk blockIdx.y; thread t takes tile slot t / 16 and solves 4 (t % 16) .. +3
+// (4 passes of 256 threads cover the 64 slots).
+template <int VT>
+__global__ __launch_bounds__(256) void k_fwd_reduce(GatherTileArgs a, FwdArgs f) {
+    const uint4 rd = a.reds[blockIdx.x];
+    const int chunk = blockIdx.y;
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+        const int t = pass * 256 + threadIdx.x;
+        const int o = t >> 4, bl = 4 * (t & 15);
+        const int idx = a.outs[rd.x * 64 + o];
+        if (idx < 0) continue;
+        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (uint32_t p = 0; p < rd.z; ++p) {
+            const float4 v = *reinterpret_cast<const float4 *>(
+                f.tile_part + ((static_cast<size_t>(chunk) * a.n_pslots + rd.y + p) * 64 + o) * 64 + bl);
+            if (p == 0) {
+                s = v;
+            } else {
+                s.x += v.x;
+                s.y += v.y;
+                s.z += v.z;
+                s.w += v.w;
+            }
+        }
+        const float v[4] = {s.x, s.y, s.z, s.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int b = chunk * 64 + bl + c;
+            const size_t oi = (static_cast<size_t>(chunk) * f.m + idx) * 64 + bl + c;
+            const float gl = f.gamma_lane ? f.gamma_lane[b] : 0.0f;
+            const float gam = f.gamma ? f.gamma[oi] : gl;
+            fwd_epilogue<VT>(f, idx, b, oi, v[c], gam, b < f.B);
         }
     }
 }
@@ -1256,6 +1312,9 @@ int back_tiles_split(const DevGatherTiles &bt) {
 
 static GatherTileArgs gather_args(const DevGatherTiles &t) {
     GatherTileArgs a{};
+    a.parts = nullptr;
+    a.reds = nullptr;
+    a.n_pslots = 0;
     a.win_off = t.win_off;
     a.rec_off = t.rec_off;
     a.records = t.records;
@@ -1288,7 +1347,8 @@ hipError_t launch_back_tiles(const DevGatherTiles &bt, int vtype, int n, int m, 
 }
 
 hipError_t launch_fwd_tiles(const DevGatherTiles &ft, int vtype, const FwdArgs &fa, hipStream_t st) {
-    if (!ft.valid || fa.Bp < 64 || fa.Bp % 64 != 0) return hipErrorInvalidValue;
+    if (!ft.valid || fa.Bp < 64 || fa.Bp % 64 != 0 || !ft.parts || (ft.n_reds > 0 && !fa.tile_part))
+        return hipErrorInvalidValue;
     GatherTileArgs a = gather_args(ft);
     a.xcd_remap = 0;
     a.split = 1;
@@ -1296,11 +1356,21 @@ hipError_t launch_fwd_tiles(const DevGatherTiles &ft, int vtype, const FwdArgs &
     a.n_out = fa.m;
     a.in = fa.x;
     a.out = nullptr;
-    const dim3 grid(static_cast<unsigned>(ft.n_tiles), static_cast<unsigned>(fa.Bp / 64));
+    a.parts = ft.parts;
+    a.reds = ft.reds;
+    a.n_pslots = ft.n_pslots;
+    const dim3 grid(static_cast<unsigned>(ft.n_parts), static_cast<unsigned>(fa.Bp / 64));
     if (vtype == VT_FP8)
         hipLaunchKernelGGL((k_gather_tiles<GM_FWD, VT_FP8>), grid, dim3(kBackThreads), 0, st, a, fa);
     else
         hipLaunchKernelGGL((k_gather_tiles<GM_FWD, VT_F32>), grid, dim3(kBackThreads), 0, st, a, fa);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || ft.n_reds == 0) return e;
+    const dim3 rgrid(static_cast<unsigned>(ft.n_reds), static_cast<unsigned>(fa.Bp / 64));
+    if (vtype == VT_FP8)
+        hipLaunchKernelGGL(k_fwd_reduce<VT_FP8>, rgrid, dim3(256), 0, st, a, fa);
+    else
+        hipLaunchKernelGGL(k_fwd_reduce<VT_F32>, rgrid, dim3(256), 0, st, a, fa);
     return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ struct Pool {
     int64_t bytes = 0;
     float *g = nullptr, *gamma = nullptr, *f = nullptr, *ft[2] = {nullptr, nullptr}, *e = nullptr;
     float *gf = nullptr;                              // A^T e of the tile kernel (or null)
+    float *tile_part = nullptr;                       // partial sums of split forward tiles (or null)
     LaneParams *lp = nullptr;
     double *mom = nullptr;
     int *lane_k = nullptr;
@@ -124,7 +125,7 @@ namespace {
 
 // Byte offsets of one pool's buffers inside its arena.
 struct PoolLayout {
-    size_t g, gamma, f, ft0, ft1, e, gf, lp, mom, k, theta, clamps, stage_in, stage_out, total;
+    size_t g, gamma, f, ft0, ft1, e, gf, tp, lp, mom, k, theta, clamps, stage_in, stage_out, total;
 };
 
 PoolLayout pool_layout(const appga_matrix *mat) {
@@ -143,6 +144,7 @@ PoolLayout pool_layout(const appga_matrix *mat) {
     L.ft1 = take(4 * d * kLanes);
     L.e = take(4 * m * kLanes);
     L.gf = mat->bt.valid ? take(4 * d * kLanes * mat->bt_split) : 0;
+    L.tp = mat->ft.valid && mat->ft.n_pslots > 0 ? take(4 * fwd_tile_part_floats(mat->ft, kLanes)) : 0;
     L.lp = take(sizeof(LaneParams) * kLanes);
     L.mom = take(sizeof(double) * 4 * kLanes);
     L.k = take(sizeof(int) * kLanes);
@@ -196,6 +198,7 @@ hipError_t enqueue_step(Pool *p, int cur) {
     fa.scale_out = 1;
     fa.fwd_wgs = mat->fwd_wgs;
     fa.clamps = p->clamps;
+    fa.tile_part = p->tile_part;
     StepArgs sa{};
     sa.row_ptr = mat->AT.row_ptr;
     sa.col = mat->AT.col;
@@ -266,6 +269,7 @@ appga_status create_pool(appga_server *srv, const appga_matrix *mat, std::unique
     p->ft[1] = reinterpret_cast<float *>(base + L.ft1);
     p->e = reinterpret_cast<float *>(base + L.e);
     p->gf = mat->bt.valid ? reinterpret_cast<float *>(base + L.gf) : nullptr;
+    p->tile_part = mat->ft.valid && mat->ft.n_pslots > 0 ? reinterpret_cast<float *>(base + L.tp) : nullptr;
     p->lp = reinterpret_cast<LaneParams *>(base + L.lp);
     p->mom = reinterpret_cast<double *>(base + L.mom);
     p->lane_k = reinterpret_cast<int *>(base + L.k);

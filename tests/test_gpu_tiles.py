@@ -39,12 +39,17 @@ def ctx():
     ap.appga_destroy(c)
 
 
-def load(ctx, A, geom, storage, back=True, fwd=True, split=None):
-    """Loads a matrix with the tile projections switched on or off."""
-    keys = ("APPGA_BACK_TILES", "APPGA_FWD_TILES", "APPGA_BACK_SPLIT")
+def load(ctx, A, geom, storage, back=True, fwd=True, split=None, part_windows=None):
+    """Loads a matrix with the tile projections switched on or off (part_windows:
+    windows per workgroup of the forward tiles, 0 = whole tiles)."""
+    keys = ("APPGA_BACK_TILES", "APPGA_FWD_TILES", "APPGA_BACK_SPLIT", "APPGA_FWD_PART_WINDOWS")
     saved = {k: os.environ.get(k) for k in keys}
     os.environ["APPGA_BACK_TILES"] = "1" if back else "0"
     os.environ["APPGA_FWD_TILES"] = "1" if fwd else "0"
+    if part_windows is not None:
+        os.environ["APPGA_FWD_PART_WINDOWS"] = str(part_windows)
+    else:
+        os.environ.pop("APPGA_FWD_PART_WINDOWS", None)
     if split is not None:
         os.environ["APPGA_BACK_SPLIT"] = str(split)
     else:
@@ -86,13 +91,18 @@ def test_back_tiles_operator(ctx, geom, storage, split):
 
 @pytest.mark.parametrize("geom", GEOMS, ids=GEOM_IDS)
 @pytest.mark.parametrize("storage", ["f32", "bf16", "fp8"])
-def test_fwd_tiles_operator(ctx, geom, storage):
+@pytest.mark.parametrize("part_windows", [0, 3])
+def test_fwd_tiles_operator(ctx, geom, storage, part_windows):
     """y = A x + gamma and e = 1 - g / max(y, tau) over the ray tiles, 64 solves
-    (and 128: two chunks), against the oracle on the dequantised matrix."""
+    (and 128: two chunks), whole tiles per workgroup or tiles split into runs of
+    3 windows (partial sums and the reduction), against the oracle on the
+    dequantised matrix."""
     A = synth.cached_matrix(geom)
-    mat = load(ctx, A, geom, storage)
+    mat = load(ctx, A, geom, storage, part_windows=part_windows)
     rng = np.random.default_rng(12)
     try:
+        info = ap.appga_matrix_tiles(mat, ap.APPGA_TILES_FORWARD)
+        assert info["valid"] == 1
         deq = ap.appga_matrix_dequantized(mat, A.nnz)
         for B in (64, 128):
             say("A x, %dx%d, %s, B %d" % (geom.n, geom.n, storage, B))
