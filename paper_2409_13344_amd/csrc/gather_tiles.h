@@ -197,8 +197,8 @@ inline bool build_back_tiles(int n, int n_angles, int n_bins, const int64_t *trp
 // consecutive bins (slot o = angle offset * kFwdTileBins + bin offset, so a
 // quad is four neighbouring bins of one angle).  Blocks whose rays all cross
 // no pixel are not tiles: their rays go, 64 to a tile, into tiles without
-// windows (sums 0), which come first (they finish at once and free their
-// slots).  A tile's windows partition the pixels its rays cross, taken in
+// windows (sums 0).  Workgroups take parts (a tile or a run of its windows)
+// longest first.  A tile's windows partition the pixels its rays cross, taken in
 // order along the tile's mean ray direction (estimated from each ray's first
 // and last stored pixel) in runs of at most kBackSlots (fewer if a window's
 // padded word lists would not fit kBackMaxWords).  Each ray's entries are
@@ -371,6 +371,20 @@ inline bool build_fwd_tiles(int n, int n_angles, int n_bins, const int64_t *row_
                                              static_cast<uint32_t>(w0 + (p + 1) * nw / np), slot});
         }
         if (np > 1) ft.n_pslots += static_cast<int>(np);
+    }
+    // dispatch order: longest parts first (the device starts workgroups in
+    // index order), so that short parts fill the slots the long ones free
+    {
+        const size_t np = ft.parts.size() / 4;
+        std::vector<size_t> ord(np);
+        std::iota(ord.begin(), ord.end(), size_t{0});
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t u, size_t v) {
+            return ft.parts[4 * u + 2] - ft.parts[4 * u + 1] > ft.parts[4 * v + 2] - ft.parts[4 * v + 1];
+        });
+        std::vector<uint32_t> sorted(ft.parts.size());
+        for (size_t i = 0; i < np; ++i)
+            for (int k = 0; k < 4; ++k) sorted[4 * i + k] = ft.parts[4 * ord[i] + k];
+        ft.parts.swap(sorted);
     }
     return ft.word.size() < (1ull << 31);
 }
