@@ -41,12 +41,13 @@ KERNELS_SRC = os.path.join(ROOT, "paper_2409_13344_amd", "csrc", "kernels.hip")
 # scaled by what the same counters read for a 1 GiB device copy (reads x2.00, writes
 # x1.00).  Valid only for the kernel source it was taken on (sha256 prefix below).
 MEASURED_TRAFFIC = {
-    "kernels_sha256_16": "4add723d988689db",
+    "kernels_sha256_16": "ec46a76d445797e2",
     "storage": "bf16",
     "read_scale": 2.0,
     "write_scale": 1.0,
-    "forward_batch": {"fetch_kib": 71165.0, "write_kib": 8400.0},
-    "step_batch": {"fetch_kib": 25731.7, "write_kib": 9216.0},
+    "fwd_tiles": {"fetch_kib": 45998.2, "write_kib": 8556.4},
+    "back_tiles": {"fetch_kib": 28269.9, "write_kib": 8192.0},
+    "step_batch": {"fetch_kib": 8571.5, "write_kib": 9216.0},
 }
 
 
