@@ -162,6 +162,24 @@ typedef struct {
 } appga_tile_info;
 appga_status appga_matrix_tiles(const appga_matrix *mat, int32_t which, appga_tile_info *out);
 
+/* Host-only emulation of a tile form (Section 2.2 products): builds the tile
+ * form that appga_load_system_matrix would build for the given CSR (F32, BF16
+ * or F16 storage; no device is used) and applies it to one vector in FP32 as
+ * the tile kernel sums it (each output's entries window by window in stored
+ * order, partial sums added in order), before any epilogue:
+ * out = A in (which = APPGA_TILES_FORWARD; in: d, out: m) or
+ * out = A^T in (APPGA_TILES_BACK; in: m, out: d).  `split`: forward -- 0 whole
+ * tiles (the default form), K > 0 runs of at most K windows, -1 the automatic
+ * run length; back projection -- workgroups per tile (1 .. groups).  *info
+ * (nullable) receives the counts; info->valid = 0 when the form does not fit
+ * the kernel's limits (then out is untouched).  Host buffers, owned by the
+ * caller.  Errors: APPGA_E_INVALID_ARG (NULL pointer, storage, which, split),
+ * APPGA_E_SHAPE / APPGA_E_DOMAIN (matrix checks as appga_validate_system_matrix). */
+appga_status appga_tiles_emulate(const appga_geometry *geom, int64_t nnz, const int64_t *row_ptr,
+                                 const int32_t *col_idx, const double *values, appga_dtype storage,
+                                 int32_t which, int32_t split, const float *in, float *out,
+                                 appga_tile_info *info);
+
 /* Launch-configuration autotuner.  Times the candidate launch configurations
  * of the projector kernels for `mat` on the device and keeps the fastest:
  * APPGA_TUNE_SINGLE -- lanes per matrix row (4..64) of the single-solve

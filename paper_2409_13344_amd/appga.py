@@ -101,6 +101,7 @@ _SIGS = {
     "appga_wait": [P, U64, P, C.POINTER(appga_stats), I32],
     "appga_server_stop": [P],
     "appga_matrix_tiles": [P, I32, P],
+    "appga_tiles_emulate": [C.POINTER(appga_geometry), I64, P, P, P, C.c_int, I32, I32, P, P, P],
 }
 
 
@@ -228,6 +229,21 @@ def appga_matrix_tiles(mat, which: int) -> dict:
     info = appga_tile_info()
     _call("appga_matrix_tiles", mat, which, C.byref(info))
     return {k: getattr(info, k) for k, _ in info._fields_ if k != "pad0"}
+
+
+def appga_tiles_emulate(A, geom, storage: str, which: int, split: int, x) -> tuple:
+    """Host emulation of the tile form of a synth.SparseMatrix: (out, counts)."""
+    g = appga_geometry(geom.n, geom.n_angles, geom.n_bins)
+    rp = _np(A.row_ptr, np.int64)
+    col = _np(A.col, np.int32)
+    val = _np(A.val, np.float64)
+    xin = _np(x, np.float32)
+    n_out = geom.m if which == APPGA_TILES_FORWARD else geom.d
+    out = np.zeros(n_out, dtype=np.float32)
+    info = appga_tile_info()
+    _call("appga_tiles_emulate", C.byref(g), A.nnz, _ptr(rp), _ptr(col), _ptr(val), DTYPES[storage],
+          which, split, _ptr(xin), _ptr(out), C.byref(info))
+    return out, {k: getattr(info, k) for k, _ in info._fields_ if k != "pad0"}
 
 
 def appga_matrix_dequantized(mat, nnz: int) -> np.ndarray:

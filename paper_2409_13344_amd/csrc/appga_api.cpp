@@ -663,6 +663,120 @@ extern "C" appga_status appga_matrix_tiles(const appga_matrix *mat, int32_t whic
     return APPGA_OK;
 }
 
+extern "C" appga_status appga_tiles_emulate(const appga_geometry *geom, int64_t nnz, const int64_t *row_ptr,
+                                           const int32_t *col_idx, const double *values, appga_dtype storage,
+                                           int32_t which, int32_t split, const float *in, float *out,
+                                           appga_tile_info *info) {
+    clear_error();
+    if (!geom || !in || !out) return fail(APPGA_E_INVALID_ARG, "NULL geometry, input or output");
+    if (storage != APPGA_F32 && storage != APPGA_BF16 && storage != APPGA_F16)
+        return fail(APPGA_E_INVALID_ARG, "emulation supports F32, BF16 and F16 storage");
+    if (which != APPGA_TILES_FORWARD && which != APPGA_TILES_BACK)
+        return fail(APPGA_E_INVALID_ARG, "which must be APPGA_TILES_FORWARD or APPGA_TILES_BACK");
+    ST_TRY(check_matrix(geom, nnz, row_ptr, col_idx, values));
+    const int n = geom->n;
+    const int64_t m = static_cast<int64_t>(geom->n_angles) * geom->n_bins, d = static_cast<int64_t>(n) * n;
+    std::vector<float> v32(nnz);
+    for (int64_t k = 0; k < nnz; ++k) {
+        const float v = static_cast<float>(values[k]);
+        v32[k] = storage == APPGA_F32 ? v
+                 : storage == APPGA_BF16 ? bf16_to_f32_host(f32_to_bf16(v))
+                                         : f16_to_f32_host(f32_to_f16(v));
+    }
+    HostGatherTiles t;
+    bool ok = false;
+    if (which == APPGA_TILES_FORWARD) {
+        ok = build_fwd_tiles(n, geom->n_angles, geom->n_bins, row_ptr, col_idx, v32.data(), t, split);
+    } else {
+        std::vector<int64_t> trp(d + 1, 0);
+        for (int64_t k = 0; k < nnz; ++k) trp[col_idx[k] + 1] += 1;
+        for (int64_t j = 0; j < d; ++j) trp[j + 1] += trp[j];
+        std::vector<int32_t> tcol(nnz);
+        std::vector<float> tv(nnz);
+        std::vector<int64_t> pos(trp.begin(), trp.end() - 1);
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+                const int64_t q = pos[col_idx[k]]++;
+                tcol[q] = static_cast<int32_t>(i);
+                tv[q] = v32[k];
+            }
+        ok = build_back_tiles(n, geom->n_angles, geom->n_bins, trp.data(), tcol.data(), tv.data(), t);
+        if (ok && (split < 1 || split > std::max(1, t.n_groups)))
+            return fail(APPGA_E_INVALID_ARG, "split must be in [1, %d]", std::max(1, t.n_groups));
+    }
+    if (info) {
+        *info = appga_tile_info{};
+        info->valid = ok ? 1 : 0;
+    }
+    if (!ok) return APPGA_OK;
+    const int64_t n_in = which == APPGA_TILES_FORWARD ? d : m, n_out = which == APPGA_TILES_FORWARD ? m : d;
+    std::fill(out, out + n_out, 0.0f);
+    // the sums of windows [w0, w1) of tile tt, as a workgroup forms them
+    std::vector<float> acc(64);
+    auto sum_windows = [&](int64_t w0, int64_t w1) -> bool {
+        std::fill(acc.begin(), acc.end(), 0.0f);
+        for (int64_t w = w0; w < w1; ++w) {
+            const uint32_t r0 = t.rec_off[w], S = t.rec_off[w + 1] - r0;
+            if (S > static_cast<uint32_t>(kBackSlots)) return false;
+            for (int o = 0; o < 64; ++o)
+                for (uint32_t k = t.rp[w * 64 + o]; k < t.rp[w * 64 + o + 1]; k += 2) {
+                    const uint32_t slot = t.word[k] / 256;
+                    if (t.word[k] % 256 || (slot >= S && slot != static_cast<uint32_t>(kBackSlots))) return false;
+                    float v;
+                    std::memcpy(&v, &t.word[k + 1], 4);
+                    const float x = slot == static_cast<uint32_t>(kBackSlots) ? 0.0f : in[t.records[r0 + slot]];
+                    acc[o] = std::fmaf(v, x, acc[o]);
+                }
+        }
+        return true;
+    };
+    for (uint32_t r : t.records)
+        if (r >= static_cast<uint64_t>(n_in)) return fail(APPGA_E_SHAPE, "tile form names input %u", r);
+    if (which == APPGA_TILES_FORWARD) {
+        std::vector<float> part(static_cast<size_t>(t.n_pslots) * 64);
+        for (size_t p = 0; p < t.parts.size() / 4; ++p) {
+            const uint32_t tt = t.parts[4 * p], slot = t.parts[4 * p + 3];
+            if (!sum_windows(t.parts[4 * p + 1], t.parts[4 * p + 2])) return fail(APPGA_E_SHAPE, "bad tile form");
+            for (int o = 0; o < 64; ++o) {
+                if (slot != kNoSlot) part[slot * 64 + o] = acc[o];
+                else if (t.outs[tt * 64 + o] >= 0) out[t.outs[tt * 64 + o]] = acc[o];
+            }
+        }
+        for (size_t r = 0; r < t.reds.size() / 4; ++r) {
+            const uint32_t tt = t.reds[4 * r], s0 = t.reds[4 * r + 1], np = t.reds[4 * r + 2];
+            for (int o = 0; o < 64; ++o) {
+                float sum = part[s0 * 64 + o];
+                for (uint32_t q = 1; q < np; ++q) sum += part[(s0 + q) * 64 + o];
+                if (t.outs[tt * 64 + o] >= 0) out[t.outs[tt * 64 + o]] = sum;
+            }
+        }
+    } else {
+        std::vector<float> tot(64);
+        for (int tt = 0; tt < t.n_tiles; ++tt) {
+            const int64_t wt0 = t.win_off[tt], nwt = t.win_off[tt + 1] - wt0;
+            std::fill(tot.begin(), tot.end(), 0.0f);
+            for (int q = 0; q < split; ++q) {   // the step kernel adds the partial sums in order
+                if (!sum_windows(wt0 + q * nwt / split, wt0 + (q + 1) * nwt / split))
+                    return fail(APPGA_E_SHAPE, "bad tile form");
+                for (int o = 0; o < 64; ++o) tot[o] += acc[o];
+            }
+            for (int o = 0; o < 64; ++o)
+                if (t.outs[tt * 64 + o] >= 0) out[t.outs[tt * 64 + o]] = tot[o];
+        }
+    }
+    if (info) {
+        info->tiles = t.n_tiles;
+        info->split = which == APPGA_TILES_BACK ? split : 1;
+        info->windows = static_cast<int64_t>(t.rec_off.size()) - 1;
+        info->records = static_cast<int64_t>(t.records.size());
+        info->entries = static_cast<int64_t>(t.word.size() / 2);
+        info->bytes = 4 * static_cast<int64_t>(t.win_off.size() + t.rec_off.size() + t.records.size() +
+                                               t.rp.size() + t.word.size() + t.outs.size() + t.parts.size() +
+                                               t.reds.size());
+    }
+    return APPGA_OK;
+}
+
 extern "C" appga_status appga_matrix_dequantized(const appga_matrix *mat, double *values_out) {
     clear_error();
     if (!mat || (!values_out && mat->nnz > 0)) return fail(APPGA_E_INVALID_ARG, "NULL argument");
