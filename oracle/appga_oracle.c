@@ -1,5 +1,6 @@
 /*
- * FP64 CPU oracle for APPGA applied to the SHOITV-regularised Poisson PET model
+ * FP64 CPU oracle for APPGA applied to the SHOITV-regularised Poisson PET model,
+ * and for FPPA / AFPPA-N / AFPPA-GN on the nonsmooth HOITV model (Section 4.3)
  * (Lin, He, Schmidtlein, Han, arXiv 2409.13344).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
@@ -11,7 +12,10 @@
  * Pinned by tests/test_oracle_*.py (Kronecker construction of B1 and B2,
  * adjoint identities, finite differences, the MLEM identity, identity-system
  * fixed points, count preservation, KKT at the minimiser of long runs,
- * Lemma 5 / Proposition 6 step inequalities, nonexpansiveness).
+ * Lemma 5 / Proposition 6 step inequalities, nonexpansiveness; for AFPPA:
+ * KKT of the nonsmooth model, perturbation optimality, the MLEM and APPGA
+ * reductions at lambda = 0, scaling equivariance, dual feasibility, and FPPA
+ * as an averaged operator in the Condat-Vu metric).
  *
  * Readings of points the paper leaves open:
  *  - the first row of D is zero (D_11 = 0), so B annihilates constants;
@@ -21,7 +25,11 @@
  *  - y_i = (A x)_i + gamma_i is floored at tau_i = 1e-6*gamma_i (1e-30 when
  *    gamma_i = 0) before the ratio; floors are counted;
  *  - f^0 = f^1 = the initial image; ACTc = sum(g) - sum(gamma);
- *  - the field-of-view disk has radius N/2 about the image centre.
+ *  - the field-of-view disk has radius N/2 about the image centre;
+ *  - AFPPA: the prox of (lambda/rho) phi uses the plain group l2 norm (phi as
+ *    defined in Section 2.1 already carries lambda), so b and c are projections
+ *    onto balls of radius lambda1 and lambda2; p_max is taken over P at f^k
+ *    (floored at 1e-30); b^0 = b^1 = 0 and c^0 = c^1 = 0.
  */
 #include <math.h>
 #include <stddef.h>
@@ -513,6 +521,209 @@ int orc_appga(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, cons
     }
     memcpy(f_out, f, sizeof(double) * d);
     if (clamps) *clamps = nclamp;
+    free(buf);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* AFPPA for the nonsmooth HOITV model (Section 4.3: FPPA with the momentum   */
+/* of eq. GNtheta or Nesterov's, eq. AFPPAiter).                             */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_MOMENTUM_NESTEROV 2
+
+/* Nesterov's sequence (Section 4.3): t_0 = 1, t_k = (1 + sqrt(1 + 4 t_{k-1}^2)) / 2. */
+double orc_t_nesterov(int k)
+{
+    double t = 1.0;
+    for (int i = 1; i <= k; ++i)
+        t = (1.0 + sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    return t;
+}
+
+/* theta_k = (t_{k-1} - 1) / t_k of Nesterov's sequence. */
+double orc_theta_nesterov(int k)
+{
+    return (orc_t_nesterov(k - 1) - 1.0) / orc_t_nesterov(k);
+}
+
+/* HOITV value (model HOTV): lambda1 sum ||((B1 f)_i, (B1 f)_{d+i})|| + lambda2 sum ||4-vector||. */
+int orc_hoitv_value(int n, double lambda1, double lambda2, const double *f, double *value)
+{
+    size_t d = (size_t)n * n;
+    double *u = (double *)malloc(sizeof(double) * 6 * d);
+    if (!u) return ORC_E_OOM;
+    double *v = u + 2 * d;
+    int st = orc_b1(n, f, u);
+    if (st == ORC_OK) st = orc_b2(n, f, v);
+    double s1 = 0.0, s2 = 0.0;
+    for (size_t i = 0; i < d && st == ORC_OK; ++i) {
+        s1 += sqrt(u[i] * u[i] + u[d + i] * u[d + i]);
+        double q = 0.0;
+        for (int c = 0; c < 4; ++c)
+            q += v[c * d + i] * v[c * d + i];
+        s2 += sqrt(q);
+    }
+    *value = lambda1 * s1 + lambda2 * s2;
+    free(u);
+    return st;
+}
+
+/* Objective of the nonsmooth model at f >= 0: fidelity + HOITV. */
+int orc_objective_hoitv(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, const double *val,
+                        const double *g, const double *gamma, double lambda1, double lambda2, const double *f,
+                        double *value)
+{
+    double *ax = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    if (!ax) return ORC_E_OOM;
+    orc_forward(m, row_ptr, col, val, f, ax);
+    double reg = 0.0;
+    int st = orc_hoitv_value(n, lambda1, lambda2, f, &reg);
+    *value = orc_fidelity_from_ax(m, ax, g, gamma) + reg;
+    free(ax);
+    return st;
+}
+
+/* (I - prox_{t ||.||_2})(z) for one group of `len` components: the projection
+ * of z onto the l2 ball of radius t, z * min(1, t / ||z||). */
+static void orc_ball_projection(double *z, int len, double t)
+{
+    double q = 0.0;
+    for (int c = 0; c < len; ++c)
+        q += z[c] * z[c];
+    double nrm = sqrt(q);
+    if (nrm > t) {
+        double s = t / nrm;
+        for (int c = 0; c < len; ++c)
+            z[c] *= s;
+    }
+}
+
+/*
+ * Runs `iterations` steps of AFPPA (momentum GN, NONE = FPPA, or NESTEROV) from
+ * f^0 = f^1 = f_init (or the disk image) with b^0 = b^1 = 0 (2d) and
+ * c^0 = c^1 = 0 (4d), and writes f^{K+1} (and b^{K+1}, c^{K+1} when b_out /
+ * c_out are given).  Each step, with theta_k from the momentum:
+ *   f~ = f + theta (f - f_prev), b~ and c~ likewise;
+ *   P = beta f^k / Lambda (EM) or the scalar fixed_p_scalar (FIXED);
+ *   rho1 = 1 / (2 * 8 * p_max), rho2 = 1 / (2 * 64 * p_max), p_max = max_j P_jj;
+ *   f^{k+1} = max(f~ - P (grad F(f~) + B1^T b~ + B2^T c~), 0);
+ *   b^{k+1} = rho1 (I - prox_{(lambda1/rho1) ||.||})(b~ / rho1 + B1 (2 f^{k+1} - f~)), per pixel
+ *   group of 2 components, and c^{k+1} likewise with rho2, lambda2 and 4 components.
+ * The prox is read with the unweighted group l2 norm (phi_1 as defined in
+ * Section 2.1 already carries lambda1), so the ball radius is lambda/rho.
+ * obj_hist (K+1): the nonsmooth objective at f^1 .. f^{K+1}; re_hist (K):
+ * ||f^{k+1} - f^k|| / ||f^{k+1}||; rho_hist (2K): rho1, rho2 per step.
+ */
+int orc_afppa(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, const double *val,
+              int n_angles, const double *g, const double *gamma, double lambda1, double lambda2,
+              double omega, double a, double b, double beta, int iterations, int momentum, int precond,
+              double fixed_p_scalar, const double *f_init, double *f_out, double *b_out, double *c_out,
+              double *obj_hist, double *re_hist, double *rho_hist, int64_t *clamps)
+{
+    if (n <= 0 || m < 0 || iterations < 0 || !row_ptr || !g || !gamma || !f_out)
+        return ORC_E_ARG;
+    if (lambda1 < 0.0 || lambda2 < 0.0 || !(beta > 0.0) || !(omega > 0.0) || omega > 1.0 || !(a > 0.0) ||
+        (omega == 1.0 && a >= 0.5) || (precond != ORC_PRECOND_EM && precond != ORC_PRECOND_FIXED) ||
+        (precond == ORC_PRECOND_FIXED && !(fixed_p_scalar > 0.0)))
+        return ORC_E_DOMAIN;
+    size_t d = (size_t)n * n;
+    double *buf = (double *)malloc(sizeof(double) * (31 * d + 2 * (size_t)m));
+    if (!buf) return ORC_E_OOM;
+    double *f = buf, *fprev = buf + d, *ft = buf + 2 * d, *gF = buf + 3 * d, *t1 = buf + 4 * d;
+    double *t2 = buf + 5 * d, *lam = buf + 6 * d, *p = buf + 7 * d, *fn = buf + 8 * d, *w = buf + 9 * d;
+    double *bq = buf + 10 * d, *bprev = buf + 12 * d, *bt = buf + 14 * d, *u = buf + 16 * d;
+    double *cq = buf + 18 * d, *cprev = buf + 22 * d, *ct = buf + 26 * d;
+    double *v = (double *)malloc(sizeof(double) * 4 * d);
+    double *y = buf + 31 * d, *e = y + m;
+    if (!v) {
+        free(buf);
+        return ORC_E_OOM;
+    }
+    int st = ORC_OK;
+    int64_t nclamp = 0;
+    if (f_init) {
+        memcpy(f, f_init, sizeof(double) * d);
+    } else {
+        st = orc_init_image(n, m, n_angles, g, gamma, f);
+    }
+    memcpy(fprev, f, sizeof(double) * d);
+    memset(bq, 0, sizeof(double) * 4 * d);      /* b and b_prev */
+    memset(cq, 0, sizeof(double) * 8 * d);      /* c and c_prev */
+    orc_em_lambda(m, (int64_t)d, row_ptr, col, val, lam);
+    if (obj_hist && st == ORC_OK)
+        st = orc_objective_hoitv(n, m, row_ptr, col, val, g, gamma, lambda1, lambda2, f, &obj_hist[0]);
+
+    for (int k = 1; k <= iterations && st == ORC_OK; ++k) {
+        /* orc_theta_nesterov rebuilds t_k from t_0 (O(k)); the runs here are short */
+        double theta = momentum == ORC_MOMENTUM_NONE       ? 0.0
+                       : momentum == ORC_MOMENTUM_NESTEROV ? orc_theta_nesterov(k)
+                                                           : orc_theta(k, a, b, omega);
+        for (size_t j = 0; j < d; ++j)
+            ft[j] = f[j] + theta * (f[j] - fprev[j]);
+        for (size_t j = 0; j < 2 * d; ++j)
+            bt[j] = bq[j] + theta * (bq[j] - bprev[j]);
+        for (size_t j = 0; j < 4 * d; ++j)
+            ct[j] = cq[j] + theta * (cq[j] - cprev[j]);
+        /* grad F at the extrapolated point */
+        orc_forward(m, row_ptr, col, val, ft, y);
+        orc_ratio(m, y, g, gamma, e, &nclamp);
+        orc_back(m, (int64_t)d, row_ptr, col, val, e, gF);
+        st = orc_b1t(n, bt, t1);
+        if (st == ORC_OK) st = orc_b2t(n, ct, t2);
+        /* preconditioner and the dual step sizes */
+        double pmax = 0.0;
+        for (size_t j = 0; j < d; ++j) {
+            p[j] = precond == ORC_PRECOND_FIXED ? fixed_p_scalar : beta * f[j] / lam[j];
+            if (p[j] > pmax) pmax = p[j];
+        }
+        if (pmax < 1e-30) pmax = 1e-30;
+        double rho1 = 1.0 / (2.0 * 8.0 * pmax), rho2 = 1.0 / (2.0 * 64.0 * pmax);
+        if (rho_hist) {
+            rho_hist[2 * (k - 1)] = rho1;
+            rho_hist[2 * (k - 1) + 1] = rho2;
+        }
+        /* primal step */
+        for (size_t j = 0; j < d; ++j) {
+            double z = ft[j] - p[j] * (gF[j] + t1[j] + t2[j]);
+            fn[j] = z > 0.0 ? z : 0.0;
+            w[j] = 2.0 * fn[j] - ft[j];
+        }
+        /* dual steps */
+        if (st == ORC_OK) st = orc_b1(n, w, u);
+        if (st == ORC_OK) st = orc_b2(n, w, v);
+        memcpy(bprev, bq, sizeof(double) * 2 * d);
+        memcpy(cprev, cq, sizeof(double) * 4 * d);
+        for (size_t i = 0; i < d && st == ORC_OK; ++i) {
+            double z1[2] = {bt[i] / rho1 + u[i], bt[d + i] / rho1 + u[d + i]};
+            orc_ball_projection(z1, 2, lambda1 / rho1);
+            bq[i] = rho1 * z1[0];
+            bq[d + i] = rho1 * z1[1];
+            double z2[4];
+            for (int c = 0; c < 4; ++c)
+                z2[c] = ct[c * d + i] / rho2 + v[c * d + i];
+            orc_ball_projection(z2, 4, lambda2 / rho2);
+            for (int c = 0; c < 4; ++c)
+                cq[c * d + i] = rho2 * z2[c];
+        }
+        if (re_hist) {
+            double dn = 0.0, nn = 0.0;
+            for (size_t j = 0; j < d; ++j) {
+                dn += (fn[j] - f[j]) * (fn[j] - f[j]);
+                nn += fn[j] * fn[j];
+            }
+            re_hist[k - 1] = nn > 0.0 ? sqrt(dn) / sqrt(nn) : 0.0;
+        }
+        memcpy(fprev, f, sizeof(double) * d);
+        memcpy(f, fn, sizeof(double) * d);
+        if (obj_hist && st == ORC_OK)
+            st = orc_objective_hoitv(n, m, row_ptr, col, val, g, gamma, lambda1, lambda2, f, &obj_hist[k]);
+    }
+    memcpy(f_out, f, sizeof(double) * d);
+    if (b_out) memcpy(b_out, bq, sizeof(double) * 2 * d);
+    if (c_out) memcpy(c_out, cq, sizeof(double) * 4 * d);
+    if (clamps) *clamps = nclamp;
+    free(v);
     free(buf);
     return st;
 }

@@ -17,10 +17,11 @@ import numpy as np
 __all__ = [
     "build_oracle", "load", "forward", "back", "b1", "b2", "b1t", "b2t", "s_eps", "reg_value",
     "grad_reg", "grad_fidelity", "objective", "em_lambda", "init_image", "theta", "appga",
-    "MOMENTUM_GN", "MOMENTUM_NONE", "PRECOND_EM", "PRECOND_EM_FROZEN", "PRECOND_FIXED",
+    "t_nesterov", "theta_nesterov", "hoitv_value", "objective_hoitv", "afppa",
+    "MOMENTUM_GN", "MOMENTUM_NONE", "MOMENTUM_NESTEROV", "PRECOND_EM", "PRECOND_EM_FROZEN", "PRECOND_FIXED",
 ]
 
-MOMENTUM_GN, MOMENTUM_NONE = 0, 1
+MOMENTUM_GN, MOMENTUM_NONE, MOMENTUM_NESTEROV = 0, 1, 2
 PRECOND_EM, PRECOND_EM_FROZEN, PRECOND_FIXED = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -78,6 +79,12 @@ def _declare(lib):
         "orc_theta": (D, [I32, D, D, D]),
         "orc_appga": (I32, [I32, I64, P, P, P, I32, P, P, D, D, D, D, D, D, D, I32, I32, I32, I32,
                             P, D, P, P, P, P, P, P, I32]),
+        "orc_t_nesterov": (D, [I32]),
+        "orc_theta_nesterov": (D, [I32]),
+        "orc_hoitv_value": (I32, [I32, D, D, P, P]),
+        "orc_objective_hoitv": (I32, [I32, I64, P, P, P, P, P, D, D, P, P]),
+        "orc_afppa": (I32, [I32, I64, P, P, P, I32, P, P, D, D, D, D, D, D, I32, I32, I32, D, P, P, P, P,
+                            P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -231,3 +238,56 @@ def appga(A, n, n_angles, g, gamma, lam1, lam2, eps, omega, iterations, a=0.125,
                           _ptr(f_out), _ptr(obj), _ptr(re), _ptr(fh), _ptr(cl), int(bool(round_f32)))
     _check(st, "appga")
     return dict(f=f_out, obj=obj, re=re, iterates=fh, clamps=int(cl[0]))
+
+
+def t_nesterov(k: int) -> float:
+    """Nesterov's sequence t_k (t_0 = 1), Section 4.3."""
+    return load().orc_t_nesterov(k)
+
+
+def theta_nesterov(k: int) -> float:
+    return load().orc_theta_nesterov(k)
+
+
+def hoitv_value(n, lam1, lam2, f) -> float:
+    """lambda1 sum ||(B1 f)_i|| + lambda2 sum ||(B2 f)_i|| (model HOTV)."""
+    out = np.zeros(1)
+    _check(load().orc_hoitv_value(n, lam1, lam2, _ptr(_f64(f)), _ptr(out)), "hoitv_value")
+    return float(out[0])
+
+
+def objective_hoitv(A, n, g, gamma, lam1, lam2, f) -> float:
+    rp, col, val = _csr(A)
+    out = np.zeros(1)
+    _check(load().orc_objective_hoitv(n, A.n_rows, _ptr(rp), _ptr(col), _ptr(val), _ptr(_f64(g)),
+                                      _ptr(_f64(gamma)), lam1, lam2, _ptr(_f64(f)), _ptr(out)),
+           "objective_hoitv")
+    return float(out[0])
+
+
+def afppa(A, n, n_angles, g, gamma, lam1, lam2, omega, iterations, a=0.125, b=1.0, beta=1.0,
+          momentum=MOMENTUM_GN, precond=PRECOND_EM, fixed_p_scalar=0.0, f_init=None, history=False,
+          duals=False):
+    """Run AFPPA (FPPA with momentum NONE, AFPPA-N with NESTEROV) in FP64 on the nonsmooth HOITV model.
+
+    Returns dict(f=f^{K+1}, b, c (duals when asked), obj=[Phi_HOITV(f^1..f^{K+1})] or None,
+    re=[RE(2..K+1)] or None, rho=(K, 2) array of (rho1, rho2) or None, clamps).
+    """
+    rp, col, val = _csr(A)
+    g, gamma = _f64(g), _f64(gamma)
+    d = n * n
+    f_out = np.empty(d)
+    b_out = np.empty(2 * d) if duals else None
+    c_out = np.empty(4 * d) if duals else None
+    obj = np.empty(iterations + 1) if history else None
+    re = np.empty(iterations) if history else None
+    rho = np.empty(2 * iterations) if history else None
+    fi = None if f_init is None else _f64(f_init)
+    cl = np.zeros(1, dtype=np.int64)
+    st = load().orc_afppa(n, A.n_rows, _ptr(rp), _ptr(col), _ptr(val), n_angles, _ptr(g), _ptr(gamma),
+                          lam1, lam2, omega, a, b, beta, iterations, momentum, precond, fixed_p_scalar,
+                          _ptr(fi), _ptr(f_out), _ptr(b_out), _ptr(c_out), _ptr(obj), _ptr(re), _ptr(rho),
+                          _ptr(cl))
+    _check(st, "afppa")
+    return dict(f=f_out, b=b_out, c=c_out, obj=obj, re=re,
+                rho=None if rho is None else rho.reshape(iterations, 2), clamps=int(cl[0]))

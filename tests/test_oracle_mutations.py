@@ -6,7 +6,9 @@ build; the suite must fail.  The list covers every step of the method: the
 difference operators, the Kronecker ordering and transposes, the smoothed
 norm and its weights, the Poisson ratio, the floor, the EM preconditioner and
 its Lambda clamp, the momentum weight and extrapolation, the prox, and the
-initial image.
+initial image; and, for the nonsmooth model, the reflection 2 f^{k+1} - f~, the
+dual balls and their radii, the dual step sizes, the dual terms of the primal
+step, Nesterov's recurrence and the HOITV group norm.
 """
 import os
 import subprocess
@@ -49,12 +51,40 @@ MUTATIONS = {
     "log_without_background": ("s -= g[i] * log(ax[i] + gamma[i]);", "s -= g[i] * log(ax[i]);"),
 }
 
+# Mistakes in the nonsmooth-model code (FPPA / AFPPA); the AFPPA pins must catch each.
+AFPPA_MUTATIONS = {
+    "afppa_reflection": ("w[j] = 2.0 * fn[j] - ft[j];", "w[j] = fn[j];"),
+    "afppa_ball_radius": ("orc_ball_projection(z1, 2, lambda1 / rho1);",
+                          "orc_ball_projection(z1, 2, lambda1);"),
+    "afppa_c_group_size": ("orc_ball_projection(z2, 4, lambda2 / rho2);",
+                           "orc_ball_projection(z2, 2, lambda2 / rho2);"),
+    "afppa_rho2_factor": ("rho2 = 1.0 / (2.0 * 64.0 * pmax);", "rho2 = 1.0 / (2.0 * 8.0 * pmax);"),
+    "afppa_pmax_extrapolated": ("fixed_p_scalar : beta * f[j] / lam[j];",
+                                "fixed_p_scalar : beta * ft[j] / lam[j];"),
+    "afppa_drop_b1t": ("double z = ft[j] - p[j] * (gF[j] + t1[j] + t2[j]);",
+                       "double z = ft[j] - p[j] * (gF[j] + t2[j]);"),
+    "afppa_dual_sign": ("z2[c] = ct[c * d + i] / rho2 + v[c * d + i];",
+                        "z2[c] = ct[c * d + i] / rho2 - v[c * d + i];"),
+    "afppa_dual_scale": ("bq[d + i] = rho1 * z1[1];", "bq[d + i] = z1[1];"),
+    "afppa_gradient_at_f": ("orc_forward(m, row_ptr, col, val, ft, y);\n        orc_ratio(m, y, g, gamma, e, &nclamp);\n        orc_back(m, (int64_t)d, row_ptr, col, val, e, gF);\n        st = orc_b1t",
+                            "orc_forward(m, row_ptr, col, val, f, y);\n        orc_ratio(m, y, g, gamma, e, &nclamp);\n        orc_back(m, (int64_t)d, row_ptr, col, val, e, gF);\n        st = orc_b1t"),
+    "nesterov_recurrence": ("t = (1.0 + sqrt(1.0 + 4.0 * t * t)) / 2.0;",
+                            "t = (1.0 + sqrt(1.0 + 2.0 * t * t)) / 2.0;"),
+    "hoitv_group": ("s1 += sqrt(u[i] * u[i] + u[d + i] * u[d + i]);",
+                    "s1 += fabs(u[i]) + fabs(u[d + i]);"),
+}
+
+
+def _cases():
+    return [(n, "test_oracle_pins.py") for n in sorted(MUTATIONS)] + \
+        [(n, "test_oracle_afppa.py") for n in sorted(AFPPA_MUTATIONS)]
+
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
-def test_pins_catch_planted_mistake(name, tmp_path):
+@pytest.mark.parametrize("name,pins", _cases())
+def test_pins_catch_planted_mistake(name, pins, tmp_path):
     src = open(SRC).read()
-    old, new = MUTATIONS[name]
+    old, new = dict(MUTATIONS, **AFPPA_MUTATIONS)[name]
     assert src.count(old) >= 1, "mutation site not found: " + name
     c_file = tmp_path / (name + ".c")
     so_file = tmp_path / (name + ".so")
@@ -63,6 +93,6 @@ def test_pins_catch_planted_mistake(name, tmp_path):
                            "-o", str(so_file), str(c_file), "-lm"])
     env = dict(os.environ, APPGA_ORACLE_LIB=str(so_file))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", pins)],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
