@@ -61,7 +61,9 @@ typedef enum {
     APPGA_FP8_E4M3_ROWSCALE = 4 /* OCP e4m3 with one FP32 scale per matrix row */
 } appga_dtype;
 
-enum { APPGA_MOMENTUM_GN = 0, APPGA_MOMENTUM_NONE = 1 };
+/* GN: theta_k from t_k = a k^omega + b (eq. GNtheta).  NONE: theta_k = 0.
+ * NESTEROV (AFPPA only): t_0 = 1, t_k = (1 + sqrt(1 + 4 t_{k-1}^2)) / 2 (Section 4.3). */
+enum { APPGA_MOMENTUM_GN = 0, APPGA_MOMENTUM_NONE = 1, APPGA_MOMENTUM_NESTEROV = 2 };
 /* EM: P = beta f^k / Lambda every iteration (eq. EM).  EM_FROZEN: updated for
  * k <= precond_freeze_iter, then kept (allowed by Section 4.1).  FIXED: P = fixed_p I. */
 enum { APPGA_PRECOND_EM = 0, APPGA_PRECOND_EM_FROZEN = 1, APPGA_PRECOND_FIXED = 2 };
@@ -234,6 +236,37 @@ appga_status appga_reconstruct_batch_device(appga_ctx *ctx, const appga_matrix *
                                             const appga_params *params, const float *d_f_init,
                                             float *d_out, void *hip_stream);
 
+/* AFPPA on the nonsmooth HOITV model (Section 4.3, model HOTV: Phi without
+ * smoothing, lambda1 sum ||(B1 f)_i|| + lambda2 sum ||(B2 f)_i||).  Per
+ * iteration, with theta_k of params.momentum (GN = AFPPA-GN, NONE = FPPA,
+ * NESTEROV = AFPPA-N) and P = beta f^k / Lambda (EM) or fixed_p (FIXED):
+ *   f~, b~, c~ = extrapolations of f, b, c with theta_k;
+ *   f^{k+1} = max(f~ - P (grad F(f~) + B1^T b~ + B2^T c~), 0);
+ *   b^{k+1} = rho1 (I - prox_{(lambda1/rho1)||.||})(b~ / rho1 + B1 (2 f^{k+1} - f~)) per
+ *   pixel (2 components), c^{k+1} likewise with rho2, lambda2 and B2 (4 components);
+ *   rho1 = 1 / (2 * 8 * p_max), rho2 = 1 / (2 * 64 * p_max), p_max = max_j P_jj
+ *   (floored at 1e-30).
+ * The prox uses the plain group l2 norm, so every dual group stays in the
+ * ball of radius lambda.  f^0 = f^1 = f_init (or the disk image of Section
+ * 4.1), b^0 = b^1 = 0, c^0 = c^1 = 0.
+ *
+ * params: as for APPGA, except that eps is not used, momentum may be NESTEROV
+ * and precond must be EM or FIXED (else APPGA_E_INVALID_ARG).  stats report
+ * the nonsmooth objective.  g, gamma, f_init, f_out and stats are as for
+ * appga_reconstruct_batch.  duals_out (B * 6 d floats, or NULL): per solve b^{K+1}
+ * (2 d: the (I kron D) plane, then the (D kron I) plane), then c^{K+1} (4 d:
+ * the four blocks of B2 in order).  B = 1 runs the single-solve kernels. */
+appga_status appga_afppa_batch(appga_ctx *ctx, const appga_matrix *mat, int32_t B,
+                               const float *g, const float *gamma, const appga_params *params,
+                               const float *f_init, float *f_out, float *duals_out,
+                               appga_stats *stats);
+/* Device-memory form of appga_afppa_batch (d_duals_out may be NULL); queues
+ * on hip_stream like appga_reconstruct_batch_device. */
+appga_status appga_afppa_batch_device(appga_ctx *ctx, const appga_matrix *mat, int32_t B,
+                                      const float *d_g, const float *d_gamma,
+                                      const appga_params *params, const float *d_f_init,
+                                      float *d_out, float *d_duals_out, void *hip_stream);
+
 /* Solve sessions: the batched solver split into its phases, so a caller can
  * advance B solves a few iterations at a time (the serving loop and the
  * benchmark do).  appga_solve_begin validates like appga_reconstruct_batch_device,
@@ -254,6 +287,15 @@ appga_status appga_solve_step(appga_solve *s, int32_t n_iters);
 appga_status appga_solve_history(const appga_solve *s, int32_t solve, int32_t cap, int32_t *iters_out,
                                  double *obj_out, int32_t *count);
 appga_status appga_solve_end(appga_solve *s, float *d_out, appga_stats *stats);
+/* An AFPPA session (same phases; the AFPPA parameter rules above; monitors and
+ * stats give the nonsmooth objective). */
+appga_status appga_afppa_begin(appga_ctx *ctx, const appga_matrix *mat, int32_t B,
+                               const float *d_g, const float *d_gamma, const appga_params *params,
+                               const float *d_f_init, void *hip_stream, appga_solve **out);
+/* The current duals (b^k, c^k) of an AFPPA session into d_duals (device, B * 6 d
+ * floats, layout of duals_out above); synchronises the session's stream.
+ * APPGA_E_INVALID_ARG for a session of the smoothed model. */
+appga_status appga_solve_duals(const appga_solve *s, float *d_duals);
 
 /* Device operators (each one kernel of the iteration, for tests and timing).
  * All arrays are HIP device memory, solve-major, FP32.

@@ -27,7 +27,7 @@ STATUS_NAMES = {
 }
 APPGA_F32, APPGA_BF16, APPGA_F16, APPGA_FP8_E4M3_ROWSCALE = 1, 2, 3, 4
 DTYPES = {"f32": APPGA_F32, "bf16": APPGA_BF16, "f16": APPGA_F16, "fp8": APPGA_FP8_E4M3_ROWSCALE}
-APPGA_MOMENTUM_GN, APPGA_MOMENTUM_NONE = 0, 1
+APPGA_MOMENTUM_GN, APPGA_MOMENTUM_NONE, APPGA_MOMENTUM_NESTEROV = 0, 1, 2
 APPGA_PRECOND_EM, APPGA_PRECOND_EM_FROZEN, APPGA_PRECOND_FIXED = 0, 1, 2
 
 
@@ -84,6 +84,10 @@ _SIGS = {
                                 C.POINTER(appga_stats)],
     "appga_reconstruct_batch_device": [P, P, I32, P, P, C.POINTER(appga_params), P, P, P],
     "appga_solve_begin": [P, P, I32, P, P, C.POINTER(appga_params), P, P, PP],
+    "appga_afppa_batch": [P, P, I32, P, P, C.POINTER(appga_params), P, P, P, C.POINTER(appga_stats)],
+    "appga_afppa_batch_device": [P, P, I32, P, P, C.POINTER(appga_params), P, P, P, P],
+    "appga_afppa_begin": [P, P, I32, P, P, C.POINTER(appga_params), P, P, PP],
+    "appga_solve_duals": [P, P],
     "appga_solve_step": [P, I32],
     "appga_solve_end": [P, P, C.POINTER(appga_stats)],
     "appga_op_forward": [P, P, I32, P, P, P, P],
@@ -197,17 +201,51 @@ def appga_destroy(ctx: int) -> None:
     _call("appga_destroy", ctx)
 
 
+# (m, d) of every loaded matrix and (B, m, d) of every open session: the device
+# entry points cannot see the length of a caller's buffer, so the wrappers
+# below check tensor sizes against them before any call reaches the device.
+_MAT_DIMS: Dict[int, tuple] = {}
+_SESS_DIMS: Dict[int, tuple] = {}
+
+
+def _need(t, count: int, what: str) -> None:
+    """A device tensor (or None) must be float32, contiguous and hold >= count elements."""
+    if t is None:
+        return
+    if str(getattr(t, "dtype", "")) != "torch.float32" or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float32 tensor" % what)
+    if t.numel() < count:
+        raise ValueError("%s holds %d elements, needs %d" % (what, t.numel(), count))
+
+
+def _dims(mat):
+    if mat not in _MAT_DIMS:
+        raise ValueError("unknown matrix handle")
+    return _MAT_DIMS[mat]
+
+
+def _host_shapes(mat, d, g, gm, fi) -> None:
+    """Host batch inputs: g (B, m), gamma (B, m) or None, f_init (B, d) or None."""
+    m, dm = _dims(mat)
+    B = g.shape[0]
+    if d != dm or g.size != B * m or (gm is not None and gm.size != B * m) or \
+            (fi is not None and fi.size != B * d):
+        raise ValueError("batch shapes do not match the matrix (m = %d, d = %d)" % (m, dm))
+
+
 def appga_load_system_matrix(ctx, n, n_angles, n_bins, row_ptr, col, val, storage="f32") -> int:
     geom = appga_geometry(n, n_angles, n_bins)
     rp, cl, vl = _np(row_ptr, np.int64), _np(col, np.int32), _np(val, np.float64)
     h = C.c_void_p()
     _call("appga_load_system_matrix", ctx, C.byref(geom), len(cl), _ptr(rp), _ptr(cl), _ptr(vl),
           DTYPES.get(storage, storage), C.byref(h))
+    _MAT_DIMS[h.value] = (n_angles * n_bins, n * n)
     return h.value
 
 
 def appga_free_system_matrix(ctx, mat) -> None:
     _call("appga_free_system_matrix", ctx, mat)
+    _MAT_DIMS.pop(mat, None)
 
 
 def appga_matrix_info(mat) -> dict:
@@ -288,6 +326,7 @@ def appga_reconstruct_batch(ctx, mat, d, g, gamma, params: Sequence[appga_params
     B = g.shape[0]
     gm = None if gamma is None else _np(gamma, np.float32)
     fi = None if f_init is None else _np(f_init, np.float32)
+    _host_shapes(mat, d, g, gm, fi)
     out = np.empty((B, d), dtype=np.float32)
     stats = (appga_stats * B)()
     _call("appga_reconstruct_batch", ctx, mat, B, _ptr(g), _ptr(gm), _param_array(params), _ptr(fi),
@@ -299,15 +338,68 @@ def appga_reconstruct_batch_device(ctx, mat, g_t, gamma_t, params: Sequence[appg
                                    f_init_t, out_t, stream=None) -> None:
     """torch tensors on the device, solve-major (B, m) / (B, d)."""
     B = len(params)
+    m, d = _dims(mat)
+    _need(g_t, B * m, "g"), _need(gamma_t, B * m, "gamma"), _need(f_init_t, B * d, "f_init")
+    _need(out_t, B * d, "out")
     _call("appga_reconstruct_batch_device", ctx, mat, B, _ptr(g_t), _ptr(gamma_t),
           _param_array(params), _ptr(f_init_t), _ptr(out_t), _stream(stream))
 
 
+def appga_afppa_batch(ctx, mat, d, g, gamma, params: Sequence[appga_params], f_init=None,
+                      duals=False):
+    """AFPPA on the nonsmooth model.  g: (B, m); gamma: (B, m) or None.  Returns
+    (f (B, d), duals (B, 6 d) or None, [stats dicts])."""
+    g = _np(g, np.float32)
+    B = g.shape[0]
+    gm = None if gamma is None else _np(gamma, np.float32)
+    fi = None if f_init is None else _np(f_init, np.float32)
+    _host_shapes(mat, d, g, gm, fi)
+    out = np.empty((B, d), dtype=np.float32)
+    du = np.empty((B, 6 * d), dtype=np.float32) if duals else None
+    stats = (appga_stats * B)()
+    _call("appga_afppa_batch", ctx, mat, B, _ptr(g), _ptr(gm), _param_array(params), _ptr(fi),
+          _ptr(out), _ptr(du), stats)
+    return out, du, [s.to_dict() for s in stats]
+
+
+def appga_afppa_batch_device(ctx, mat, g_t, gamma_t, params: Sequence[appga_params], f_init_t,
+                             out_t, duals_t=None, stream=None) -> None:
+    B = len(params)
+    m, d = _dims(mat)
+    _need(g_t, B * m, "g"), _need(gamma_t, B * m, "gamma"), _need(f_init_t, B * d, "f_init")
+    _need(out_t, B * d, "out"), _need(duals_t, B * 6 * d, "duals")
+    _call("appga_afppa_batch_device", ctx, mat, B, _ptr(g_t), _ptr(gamma_t), _param_array(params),
+          _ptr(f_init_t), _ptr(out_t), _ptr(duals_t), _stream(stream))
+
+
+def appga_afppa_begin(ctx, mat, g_t, gamma_t, params: Sequence[appga_params], f_init_t=None,
+                      stream=None) -> int:
+    B = len(params)
+    m, d = _dims(mat)
+    _need(g_t, B * m, "g"), _need(gamma_t, B * m, "gamma"), _need(f_init_t, B * d, "f_init")
+    h = C.c_void_p()
+    _call("appga_afppa_begin", ctx, mat, B, _ptr(g_t), _ptr(gamma_t),
+          _param_array(params), _ptr(f_init_t), _stream(stream), C.byref(h))
+    _SESS_DIMS[h.value] = (B, m, d)
+    return h.value
+
+
+def appga_solve_duals(sess, duals_t) -> None:
+    if sess in _SESS_DIMS:
+        B, _, d = _SESS_DIMS[sess]
+        _need(duals_t, B * 6 * d, "duals")
+    _call("appga_solve_duals", sess, _ptr(duals_t))
+
+
 def appga_solve_begin(ctx, mat, g_t, gamma_t, params: Sequence[appga_params], f_init_t=None,
                       stream=None) -> int:
+    B = len(params)
+    m, d = _dims(mat)
+    _need(g_t, B * m, "g"), _need(gamma_t, B * m, "gamma"), _need(f_init_t, B * d, "f_init")
     h = C.c_void_p()
-    _call("appga_solve_begin", ctx, mat, len(params), _ptr(g_t), _ptr(gamma_t),
+    _call("appga_solve_begin", ctx, mat, B, _ptr(g_t), _ptr(gamma_t),
           _param_array(params), _ptr(f_init_t), _stream(stream), C.byref(h))
+    _SESS_DIMS[h.value] = (B, m, d)
     return h.value
 
 
@@ -326,8 +418,14 @@ def appga_solve_history(sess, solve: int):
 
 
 def appga_solve_end(sess, out_t, B: int) -> List[dict]:
+    if sess in _SESS_DIMS:
+        Bs, _, d = _SESS_DIMS[sess]
+        if B != Bs:
+            raise ValueError("session has %d solves, not %d" % (Bs, B))
+        _need(out_t, B * d, "out")
     stats = (appga_stats * B)()
     _call("appga_solve_end", sess, _ptr(out_t), stats)
+    _SESS_DIMS.pop(sess, None)
     return [s.to_dict() for s in stats]
 
 

@@ -788,14 +788,14 @@ extern "C" appga_status appga_matrix_dequantized(const appga_matrix *mat, double
 
 namespace appga {
 
-appga_status validate_params(const appga_params *p) {
+appga_status validate_params(const appga_params *p, bool afppa) {
     if (!p) return fail(APPGA_E_INVALID_ARG, "params is NULL");
     const double vals[] = {p->lambda1, p->lambda2, p->eps, p->omega, p->a, p->b, p->beta,
                            p->fixed_p, p->gamma_scalar};
     for (double v : vals)
         if (!std::isfinite(v)) return fail(APPGA_E_DOMAIN, "non-finite parameter");
     if (p->lambda1 < 0 || p->lambda2 < 0) return fail(APPGA_E_DOMAIN, "lambda must be >= 0");
-    if (!(p->eps > 0)) return fail(APPGA_E_DOMAIN, "eps must be > 0");
+    if (!afppa && !(p->eps > 0)) return fail(APPGA_E_DOMAIN, "eps must be > 0");
     if (!(p->omega > 0) || p->omega > 1) return fail(APPGA_E_DOMAIN, "omega must be in (0, 1]");
     if (!(p->a > 0)) return fail(APPGA_E_DOMAIN, "a must be > 0");
     if (p->omega == 1.0 && p->a >= 0.5) return fail(APPGA_E_DOMAIN, "omega = 1 needs a < 1/2");
@@ -806,11 +806,14 @@ appga_status validate_params(const appga_params *p) {
     }
     if (!(p->beta > 0)) return fail(APPGA_E_DOMAIN, "beta must be > 0");
     if (p->iterations < 0) return fail(APPGA_E_DOMAIN, "iterations must be >= 0");
-    if (p->momentum != APPGA_MOMENTUM_GN && p->momentum != APPGA_MOMENTUM_NONE)
+    if (p->momentum != APPGA_MOMENTUM_GN && p->momentum != APPGA_MOMENTUM_NONE &&
+        !(afppa && p->momentum == APPGA_MOMENTUM_NESTEROV))
         return fail(APPGA_E_INVALID_ARG, "unknown momentum %d", p->momentum);
     if (p->precond != APPGA_PRECOND_EM && p->precond != APPGA_PRECOND_EM_FROZEN &&
         p->precond != APPGA_PRECOND_FIXED)
         return fail(APPGA_E_INVALID_ARG, "unknown preconditioner %d", p->precond);
+    if (afppa && p->precond == APPGA_PRECOND_EM_FROZEN)
+        return fail(APPGA_E_INVALID_ARG, "AFPPA takes the EM or the fixed preconditioner");
     if (p->precond == APPGA_PRECOND_FIXED && !(p->fixed_p > 0))
         return fail(APPGA_E_DOMAIN, "fixed_p must be > 0");
     if (p->gamma_scalar < 0) return fail(APPGA_E_DOMAIN, "gamma_scalar must be >= 0");
@@ -828,6 +831,15 @@ appga_status validate_data(const float *v, int64_t n, const char *what) {
 
 double theta_of(const appga_params &p, int k) {
     if (p.momentum == APPGA_MOMENTUM_NONE || k < 1) return 0.0;
+    if (p.momentum == APPGA_MOMENTUM_NESTEROV) {
+        // t_0 = 1, t_k = (1 + sqrt(1 + 4 t_{k-1}^2)) / 2; theta_k = (t_{k-1} - 1) / t_k
+        double tp = 1.0, t = 1.0;
+        for (int i = 1; i <= k; ++i) {
+            tp = t;
+            t = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+        }
+        return (tp - 1.0) / t;
+    }
     const double tkm1 = p.a * std::pow(static_cast<double>(k - 1), p.omega) + p.b;
     const double tk = p.a * std::pow(static_cast<double>(k), p.omega) + p.b;
     return (tkm1 - 1.0) / tk;
@@ -847,7 +859,7 @@ static appga_status sess_alloc(appga_solve *s) {
                              sum_blocks(static_cast<int>(m)), sb});
     const int Bp = pad_lanes(B);
     s->Bp = Bp;
-    s->part_len = static_cast<size_t>(nb) * Bp * 2;
+    s->part_len = static_cast<size_t>(std::max(nb, afppa_blocks(s->mat->geom.n, Bp))) * Bp * 2;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -863,7 +875,14 @@ static appga_status sess_alloc(appga_solve *s) {
     const size_t o_e = take(sizeof(float) * m * Bp);
     const size_t o_pb = s->need_pbuf ? take(sizeof(float) * d * Bp) : 0;
     const bool tiles = B > 1 && s->mat->bt.valid;
-    const size_t o_gf = tiles ? take(sizeof(float) * d * Bp * s->mat->bt_split) : 0;
+    // AFPPA takes A^T e as its own pass in every layout (split partial sums with tiles)
+    s->gf_split = tiles ? s->mat->bt_split : 1;
+    const bool need_gf = tiles || s->afppa;
+    const size_t o_gf = need_gf ? take(sizeof(float) * d * Bp * s->gf_split) : 0;
+    const size_t o_w = s->afppa ? take(sizeof(float) * d * Bp) : 0;
+    const size_t o_y = s->afppa ? take(sizeof(float) * 6 * d * Bp) : 0;
+    const size_t o_yb = s->afppa ? take(sizeof(float) * 6 * d * Bp) : 0;
+    const size_t o_pm = s->afppa ? take(sizeof(unsigned) * 3 * Bp) : 0;
     const size_t n_tp = B > 1 && s->mat->ft.valid ? fwd_tile_part_floats(s->mat->ft, Bp) : 0;
     const size_t o_tp = n_tp ? take(sizeof(float) * n_tp) : 0;
     const size_t o_lp = take(sizeof(LaneParams) * Bp);
@@ -886,7 +905,13 @@ static appga_status sess_alloc(appga_solve *s) {
     s->ft[1] = reinterpret_cast<float *>(base + o_ft1);
     s->e = reinterpret_cast<float *>(base + o_e);
     s->pbuf = s->need_pbuf ? reinterpret_cast<float *>(base + o_pb) : nullptr;
-    s->gf = tiles ? reinterpret_cast<float *>(base + o_gf) : nullptr;
+    s->gf = need_gf ? reinterpret_cast<float *>(base + o_gf) : nullptr;
+    if (s->afppa) {
+        s->w = reinterpret_cast<float *>(base + o_w);
+        s->ydual = reinterpret_cast<float *>(base + o_y);
+        s->ybar = reinterpret_cast<float *>(base + o_yb);
+        s->pm = reinterpret_cast<unsigned *>(base + o_pm);
+    }
     s->tile_part = n_tp ? reinterpret_cast<float *>(base + o_tp) : nullptr;
     s->lp = reinterpret_cast<LaneParams *>(base + o_lp);
     s->theta = reinterpret_cast<float *>(base + o_th);
@@ -960,12 +985,12 @@ appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> 
 
 appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const float *d_g,
                         const float *d_gamma, const appga_params *params, const float *d_f_init,
-                        hipStream_t st, appga_solve **out) {
+                        hipStream_t st, appga_solve **out, bool afppa) {
     if (!ctx || !mat || !params || !d_g || !out)
         return fail(APPGA_E_INVALID_ARG, "NULL ctx, matrix, params, data or output");
     if (B <= 0) return fail(APPGA_E_INVALID_ARG, "B must be >= 1");
     if (mat->ctx != ctx) return fail(APPGA_E_INVALID_ARG, "matrix belongs to another context");
-    for (int b = 0; b < B; ++b) ST_TRY(validate_params(&params[b]));
+    for (int b = 0; b < B; ++b) ST_TRY(validate_params(&params[b], afppa));
     for (int b = 1; b < B; ++b)
         if (params[b].precond != params[0].precond ||
             params[b].precond_freeze_iter != params[0].precond_freeze_iter)
@@ -977,6 +1002,7 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
     s->B = B;
     s->st = st ? st : ctx->stream;
     s->prm.assign(params, params + B);
+    s->afppa = afppa;
     s->has_gamma = d_gamma != nullptr;
     s->need_pbuf = params[0].precond == APPGA_PRECOND_EM_FROZEN;
     s->monitor_every = params[0].monitor_every;
@@ -1011,8 +1037,9 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
     std::vector<float> gl(Bp, 0.0f);
     for (int b = 0; b < B; ++b) {
         const appga_params &p = params[b];
+        // eps = 0 makes the objective kernels evaluate the nonsmooth HOITV model
         lp[b] = LaneParams{static_cast<float>(p.lambda1), static_cast<float>(p.lambda2),
-                           static_cast<float>(p.eps), static_cast<float>(p.beta),
+                           afppa ? 0.0f : static_cast<float>(p.eps), static_cast<float>(p.beta),
                            static_cast<float>(p.fixed_p), 0.f, 0.f, 0.f};
         gl[b] = static_cast<float>(p.gamma_scalar);
     }
@@ -1022,6 +1049,13 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
         he = hipMemcpyAsync(s->gamma_lane, gl.data(), sizeof(float) * Bp, hipMemcpyHostToDevice, s->st);
     if (he == hipSuccess)
         he = launch_fill(reinterpret_cast<float *>(s->clamps), 2 * static_cast<size_t>(Bp), 0.0f, s->st);
+    // AFPPA: b^0 = b^1 = 0, c^0 = c^1 = 0, max accumulators at 0 (the bits of +0.0f)
+    if (he == hipSuccess && afppa)
+        he = launch_fill(s->ydual, static_cast<size_t>(6) * d * Bp, 0.0f, s->st);
+    if (he == hipSuccess && afppa)
+        he = launch_fill(s->ybar, static_cast<size_t>(6) * d * Bp, 0.0f, s->st);
+    if (he == hipSuccess && afppa)
+        he = launch_fill(reinterpret_cast<float *>(s->pm), 3 * static_cast<size_t>(Bp), 0.0f, s->st);
     // initial image f^0 = f^1
     if (he == hipSuccess) {
         if (d_f_init) {
@@ -1080,9 +1114,111 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
     return APPGA_OK;
 }
 
+// One AFPPA iteration per pass (Section 4.3): the ratio forward projection at
+// f~^k, the back projection A^T e (tile partial sums for batches with tiles,
+// else the step kernel's gather), then the primal and the dual kernels.
+static appga_status afppa_step(appga_solve *s, int n_iters) {
+    const appga_matrix *mat = s->mat;
+    const int B = s->B, Bp = s->Bp;
+    const appga_params &p0 = s->prm[0];
+    for (int it = 0; it < n_iters; ++it) {
+        const int k = s->k;
+        if (k + 1 > s->theta_base + s->theta_cap) ST_TRY(sess_theta(s, k));
+        FwdArgs fa{};
+        fa.row_ptr = mat->A.row_ptr;
+        fa.col = mat->A.col;
+        fa.val = mat->A.val;
+        fa.row_scale = mat->A.row_scale;
+        fa.col32 = mat->A.col32;
+        fa.nnz_padded = mat->A.nnz_padded;
+        fa.m = mat->A.n_rows;
+        fa.n_x = mat->A.n_cols;
+        fa.B = B;
+        fa.Bp = Bp;
+        fa.x = s->ft[s->cur];
+        fa.g = s->g;
+        fa.gamma = s->gamma;
+        fa.gamma_lane = s->gamma_lane;
+        fa.out = s->e;
+        fa.mode = FM_RATIO;
+        fa.scale_out = 1;
+        fa.fwd_wgs = mat->fwd_wgs;
+        fa.clamps = s->clamps;
+        fa.tile_part = s->tile_part;
+        const char *fname = B == 1 ? "forward_single" : (forward_uses_tiles(mat, fa) ? "fwd_tiles" : "forward_batch");
+        HIP_TRY(timed_launch(s->ctx, fname, s->st, [&] { return launch_forward_mat(mat, fa, s->st); }));
+        if (B > 1 && mat->bt.valid) {
+            HIP_TRY(timed_launch(s->ctx, "back_tiles", s->st, [&] {
+                return launch_back_tiles(mat->bt, mat->AT.vtype, mat->geom.n, mat->A.n_rows, Bp,
+                                         mat->bt_remap, mat->bt_split, s->e, s->gf, s->st);
+            }));
+        } else {
+            StepArgs sa{};
+            sa.row_ptr = mat->AT.row_ptr;
+            sa.col = mat->AT.col;
+            sa.val = mat->AT.val;
+            sa.row_scale = mat->AT.row_scale;
+            sa.col32 = mat->AT.col32;
+            sa.nnz_padded = mat->AT.nnz_padded;
+            sa.n = mat->geom.n;
+            sa.m = mat->A.n_rows;
+            sa.B = B;
+            sa.Bp = Bp;
+            sa.e = s->e;
+            sa.ft = s->ft[s->cur];
+            sa.f = s->f;
+            sa.ft_next = s->ft[s->cur ^ 1];
+            sa.lam = mat->lam;
+            sa.lp = s->lp;
+            sa.theta_next = s->theta;
+            sa.pmode = PM_EM;
+            sa.out_mode = SO_BACK;
+            sa.out = s->gf;
+            sa.tiles_x = (mat->geom.n + 3) / 4;
+            sa.xcd_remap = mat->xcd_remap;
+            HIP_TRY(timed_launch(s->ctx, B == 1 ? "back_single" : "back_batch", s->st,
+                                 [&] { return launch_step(mat->AT, sa, mat->group_back, s->st); }));
+        }
+        AfppaArgs aa{};
+        aa.n = mat->geom.n;
+        aa.B = B;
+        aa.Bp = Bp;
+        aa.gf = s->gf;
+        aa.gf_split = s->gf_split;
+        aa.f = s->f;
+        aa.ft = s->ft[s->cur];
+        aa.ft_next = s->ft[s->cur ^ 1];
+        aa.w = s->w;
+        aa.y = s->ydual;
+        aa.ybar = s->ybar;
+        aa.lam = mat->lam;
+        aa.lp = s->lp;
+        aa.theta_next = s->theta + static_cast<size_t>(k + 1 - s->theta_base) * Bp;
+        aa.pmode = p0.precond == APPGA_PRECOND_FIXED ? PM_FIXED : PM_EM;
+        aa.pmax_acc = s->pm + static_cast<size_t>(k % 3) * Bp;
+        aa.pmax_in = aa.pmax_acc;
+        aa.pmax_clear = s->pm + static_cast<size_t>((k + 1) % 3) * Bp;
+        aa.re_part = (it == n_iters - 1) ? s->part : nullptr;
+        HIP_TRY(timed_launch(s->ctx, "afppa_primal", s->st, [&] { return launch_afppa_primal(aa, s->st); }));
+        HIP_TRY(timed_launch(s->ctx, "afppa_dual", s->st, [&] { return launch_afppa_dual(aa, s->st); }));
+        s->cur ^= 1;
+        s->k += 1;
+        s->re_valid = (it == n_iters - 1);
+        s->re_blocks = afppa_blocks(mat->geom.n, Bp);
+        if (s->monitor_every > 0 && (s->k - 1) % s->monitor_every == 0) {
+            std::vector<double> obj;
+            ST_TRY(sess_objective(s, s->f, obj, s->mpart, s->mred));
+            s->hist_k.push_back(s->k);
+            s->hist_obj.insert(s->hist_obj.end(), obj.begin(), obj.end());
+        }
+    }
+    return APPGA_OK;
+}
+
 appga_status sess_step(appga_solve *s, int n_iters) {
     if (!s) return fail(APPGA_E_INVALID_ARG, "session is NULL");
     if (n_iters < 0) return fail(APPGA_E_INVALID_ARG, "n_iters must be >= 0");
+    if (s->afppa) return afppa_step(s, n_iters);
     const appga_matrix *mat = s->mat;
     const int B = s->B;
     const appga_params &p0 = s->prm[0];
@@ -1154,6 +1290,7 @@ appga_status sess_step(appga_solve *s, int n_iters) {
         s->cur ^= 1;
         s->k += 1;
         s->re_valid = (it == n_iters - 1);
+        s->re_blocks = step_blocks(mat->geom.n, B);
         if (s->monitor_every > 0 && (s->k - 1) % s->monitor_every == 0) {
             std::vector<double> obj;
             ST_TRY(sess_objective(s, s->f, obj, s->mpart, s->mred));
@@ -1172,7 +1309,7 @@ appga_status sess_end(appga_solve *s, float *d_out, appga_stats *stats, bool fre
     appga_status rs = APPGA_OK;
     std::vector<double> re(2 * B, 0.0);
     if (s->re_valid) {
-        HIP_TRY(launch_reduce_partials(s->part, step_blocks(n, B), B, 2, s->red + 2 * B, s->st));
+        HIP_TRY(launch_reduce_partials(s->part, s->re_blocks, B, 2, s->red + 2 * B, s->st));
         HIP_TRY(hipMemcpyAsync(re.data(), s->red + 2 * B, sizeof(double) * 2 * B,
                                hipMemcpyDeviceToHost, s->st));
     }
@@ -1261,17 +1398,32 @@ extern "C" appga_status appga_solve_end(appga_solve *s, float *d_out, appga_stat
 
 namespace {
 
+// The duals (b, c) of an AFPPA session, solve-major [B][6 d] (b: 2 d, then c: 4 d).
+appga_status sess_duals(const appga_solve *s, float *d_duals) {
+    if (!s) return fail(APPGA_E_INVALID_ARG, "session is NULL");
+    if (!s->afppa) return fail(APPGA_E_INVALID_ARG, "not an AFPPA session");
+    if (!d_duals) return fail(APPGA_E_INVALID_ARG, "NULL output");
+    const int64_t len = 6 * s->mat->A.n_cols;
+    if (s->Bp == 1)
+        HIP_TRY(hipMemcpyAsync(d_duals, s->ydual, sizeof(float) * len, hipMemcpyDeviceToDevice, s->st));
+    else
+        HIP_TRY(launch_from_lanes(s->ydual, d_duals, static_cast<int>(len), s->B, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    return APPGA_OK;
+}
+
 appga_status run_batch_device(appga_ctx *ctx, const appga_matrix *mat, int B, const float *d_g,
                               const float *d_gamma, const appga_params *params,
                               const float *d_f_init, float *d_out, hipStream_t st,
-                              appga_stats *stats) {
-    for (int b = 0; b < B; ++b) ST_TRY(validate_params(&params[b]));
+                              appga_stats *stats, bool afppa = false, float *d_duals = nullptr) {
+    for (int b = 0; b < B; ++b) ST_TRY(validate_params(&params[b], afppa));
     for (int b = 1; b < B; ++b)
         if (params[b].iterations != params[0].iterations)
             return fail(APPGA_E_INVALID_ARG, "all solves of a batch need the same iteration count");
     appga_solve *s = nullptr;
-    ST_TRY(sess_begin(ctx, mat, B, d_g, d_gamma, params, d_f_init, st, &s));
+    ST_TRY(sess_begin(ctx, mat, B, d_g, d_gamma, params, d_f_init, st, &s, afppa));
     appga_status rs = sess_step(s, params[0].iterations);
+    if (rs == APPGA_OK && d_duals) rs = sess_duals(s, d_duals);
     if (rs == APPGA_OK) rs = sess_end(s, d_out, stats, false);
     sess_free(s);
     return rs;
@@ -1279,22 +1431,26 @@ appga_status run_batch_device(appga_ctx *ctx, const appga_matrix *mat, int B, co
 
 appga_status run_batch_host(appga_ctx *ctx, const appga_matrix *mat, int B, const float *g,
                             const float *gamma, const appga_params *params, const float *f_init,
-                            float *f_out, appga_stats *stats) {
+                            float *f_out, appga_stats *stats, bool afppa = false,
+                            float *duals_out = nullptr) {
     if (!ctx || !mat || !g || !params || !f_out)
         return fail(APPGA_E_INVALID_ARG, "NULL ctx, matrix, data, params or output");
     if (B <= 0) return fail(APPGA_E_INVALID_ARG, "B must be >= 1");
     const int64_t m = mat->A.n_rows, d = mat->A.n_cols;
-    for (int b = 0; b < B; ++b) ST_TRY(validate_params(&params[b]));
+    for (int b = 0; b < B; ++b) ST_TRY(validate_params(&params[b], afppa));
     ST_TRY(validate_data(g, m * B, "sinogram"));
     if (gamma) ST_TRY(validate_data(gamma, m * B, "background"));
     if (f_init) ST_TRY(validate_data(f_init, d * B, "f_init"));
     HIP_TRY(hipSetDevice(ctx->device));
     float *buf = nullptr;
-    const size_t nf = static_cast<size_t>(m) * B * (gamma ? 2 : 1) + static_cast<size_t>(d) * B * (f_init ? 2 : 1);
+    const size_t ndual = duals_out ? static_cast<size_t>(6) * d * B : 0;
+    const size_t nf = static_cast<size_t>(m) * B * (gamma ? 2 : 1) + static_cast<size_t>(d) * B * (f_init ? 2 : 1) +
+                      ndual;
     HIP_TRY(hipMalloc(&buf, sizeof(float) * nf));
     float *dg = buf, *dgam = gamma ? buf + m * B : nullptr;
     float *dfi = f_init ? buf + m * B * (gamma ? 2 : 1) : nullptr;
     float *dout = buf + m * B * (gamma ? 2 : 1) + (f_init ? d * B : 0);
+    float *ddual = duals_out ? dout + d * B : nullptr;
     hipStream_t st = ctx->stream;
     appga_status rs = APPGA_OK;
     hipError_t he = hipMemcpyAsync(dg, g, sizeof(float) * m * B, hipMemcpyHostToDevice, st);
@@ -1306,12 +1462,14 @@ appga_status run_batch_host(appga_ctx *ctx, const appga_matrix *mat, int B, cons
         rs = fail(APPGA_E_DEVICE, "upload failed: %s", hipGetErrorString(he));
     } else {
         std::vector<appga_stats> tmp(B);
-        rs = run_batch_device(ctx, mat, B, dg, dgam, params, dfi, dout, st, tmp.data());
+        rs = run_batch_device(ctx, mat, B, dg, dgam, params, dfi, dout, st, tmp.data(), afppa, ddual);
         if (rs == APPGA_OK || rs == APPGA_E_NONFINITE) {
             if (stats) std::memcpy(stats, tmp.data(), sizeof(appga_stats) * B);
         }
         if (rs == APPGA_OK) {
             he = hipMemcpy(f_out, dout, sizeof(float) * d * B, hipMemcpyDeviceToHost);
+            if (he == hipSuccess && duals_out)
+                he = hipMemcpy(duals_out, ddual, sizeof(float) * ndual, hipMemcpyDeviceToHost);
             if (he != hipSuccess) rs = fail(APPGA_E_DEVICE, "download failed: %s", hipGetErrorString(he));
         }
     }
@@ -1364,6 +1522,40 @@ extern "C" appga_status appga_reconstruct_batch_device(appga_ctx *ctx, const app
     if (B <= 0) return fail(APPGA_E_INVALID_ARG, "B must be >= 1");
     return run_batch_device(ctx, mat, B, d_g, d_gamma, params, d_f_init, d_out,
                             static_cast<hipStream_t>(hip_stream), nullptr);
+}
+
+extern "C" appga_status appga_afppa_batch(appga_ctx *ctx, const appga_matrix *mat, int32_t B,
+                                          const float *g, const float *gamma, const appga_params *params,
+                                          const float *f_init, float *f_out, float *duals_out,
+                                          appga_stats *stats) {
+    clear_error();
+    return run_batch_host(ctx, mat, B, g, gamma, params, f_init, f_out, stats, true, duals_out);
+}
+
+extern "C" appga_status appga_afppa_batch_device(appga_ctx *ctx, const appga_matrix *mat, int32_t B,
+                                                 const float *d_g, const float *d_gamma,
+                                                 const appga_params *params, const float *d_f_init,
+                                                 float *d_out, float *d_duals_out, void *hip_stream) {
+    clear_error();
+    if (!ctx || !mat || !d_g || !params || !d_out)
+        return fail(APPGA_E_INVALID_ARG, "NULL ctx, matrix, data, params or output");
+    if (B <= 0) return fail(APPGA_E_INVALID_ARG, "B must be >= 1");
+    return run_batch_device(ctx, mat, B, d_g, d_gamma, params, d_f_init, d_out,
+                            static_cast<hipStream_t>(hip_stream), nullptr, true, d_duals_out);
+}
+
+extern "C" appga_status appga_afppa_begin(appga_ctx *ctx, const appga_matrix *mat, int32_t B,
+                                          const float *d_g, const float *d_gamma,
+                                          const appga_params *params, const float *d_f_init,
+                                          void *hip_stream, appga_solve **out) {
+    clear_error();
+    return sess_begin(ctx, mat, B, d_g, d_gamma, params, d_f_init, static_cast<hipStream_t>(hip_stream),
+                      out, true);
+}
+
+extern "C" appga_status appga_solve_duals(const appga_solve *s, float *d_duals) {
+    clear_error();
+    return sess_duals(s, d_duals);
 }
 
 // ------------------------------------------------------------ operators ---

@@ -76,6 +76,14 @@ struct appga_solve {
     std::vector<int32_t> hist_k;
     std::vector<double> hist_obj;   // [entry][B]
     std::chrono::steady_clock::time_point t0;
+    // AFPPA sessions (Section 4.3): w = 2 f^{k+1} - f~, the duals (b, c) and their
+    // extrapolation as 6 components per pixel, and three rotating per-solve
+    // accumulators of max P (FP32 bits)
+    bool afppa = false;
+    float *w = nullptr, *ydual = nullptr, *ybar = nullptr;
+    unsigned *pm = nullptr;
+    int gf_split = 1;
+    int re_blocks = 0;   // workgroups that wrote the RE partial sums of the last step
 };
 
 // Returns APPGA_E_DEVICE (with the failing call in the message) when a HIP
@@ -97,7 +105,9 @@ namespace appga {
 
 appga_status fail(appga_status st, const char *fmt, ...);
 void clear_error();
-appga_status validate_params(const appga_params *p);
+// afppa: the nonsmooth model (Section 4.3): eps is unused, Nesterov momentum is
+// allowed, the frozen EM preconditioner is not.
+appga_status validate_params(const appga_params *p, bool afppa = false);
 appga_status validate_data(const float *v, int64_t n, const char *what);
 double theta_of(const appga_params &p, int k);
 hipError_t timed_launch(appga_ctx *ctx, const char *name, hipStream_t st,
@@ -105,7 +115,7 @@ hipError_t timed_launch(appga_ctx *ctx, const char *name, hipStream_t st,
 
 appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const float *d_g,
                         const float *d_gamma, const appga_params *params, const float *d_f_init,
-                        hipStream_t st, appga_solve **out);
+                        hipStream_t st, appga_solve **out, bool afppa = false);
 appga_status sess_step(appga_solve *s, int n_iters);
 appga_status sess_end(appga_solve *s, float *d_out, appga_stats *stats, bool free_session);
 appga_status tune_matrix(appga_ctx *ctx, appga_matrix *mat, int flags, appga_tuning *out);

@@ -188,6 +188,39 @@ struct StepArgs {
     int xcd_remap;           // 1: map workgroups to spatially compact tile blocks per XCD
 };
 
+// One AFPPA iteration after the ratio forward projection and the back
+// projection (Section 4.3).  The duals (b, c) are one vector of 6 components
+// per pixel and solve: b as components 0, 1 ((I (x) D) and (D (x) I) groups),
+// c as components 2..5 (the four blocks of B2), each component a plane of d
+// values (component-major: index k * d + j), in the layout of Bp (plain for
+// Bp == 1, else the lane layout of a vector of length 6 d).
+struct AfppaArgs {
+    int n;                     // image side N (d = N * N)
+    int B;                     // solves
+    int Bp;                    // 1, or the padded lane count (multiple of 64)
+    const float *gf;           // A^T e as gf_split partial sums [gf_split][d][Bp], added in order
+    int gf_split;
+    float *f;                  // [d] f^k in, f^{k+1} out
+    const float *ft;           // [d] f~^k
+    float *ft_next;            // [d] f~^{k+1}
+    float *w;                  // [d] 2 f^{k+1} - f~^k (primal writes, dual reads)
+    float *y;                  // [6 d] duals (b^k, c^k) in, (b^{k+1}, c^{k+1}) out (dual)
+    float *ybar;               // [6 d] extrapolated duals: read by the primal, rewritten by the dual
+    const float *lam;          // [d] Lambda
+    const LaneParams *lp;      // [Bp]
+    const float *theta_next;   // [Bp] theta_{k+1}
+    int pmode;                 // PM_EM or PM_FIXED
+    unsigned *pmax_acc;        // [Bp] primal: running max of P at f^k (FP32 bits of values >= 0)
+    const unsigned *pmax_in;   // [Bp] dual: the max the primal of this iteration accumulated
+    unsigned *pmax_clear;      // [Bp] dual: accumulator of the next iteration, set to 0 here
+    double *re_part;           // primal: [blocks][Bp][2] sum (f^{k+1} - f^k)^2, sum (f^{k+1})^2 (or null)
+};
+
+// Workgroups of the AFPPA kernels (RE partial sums per workgroup).
+int afppa_blocks(int n, int Bp);
+hipError_t launch_afppa_primal(const AfppaArgs &a, hipStream_t st);
+hipError_t launch_afppa_dual(const AfppaArgs &a, hipStream_t st);
+
 // B > 1 back projection out = A^T e over the pixel tiles (lane layout, Bp / 64
 // chunks, `split` partial sums).
 hipError_t launch_back_tiles(const DevGatherTiles &bt, int vtype, int n, int m, int Bp, int xcd_remap,

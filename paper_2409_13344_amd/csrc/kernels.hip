@@ -612,6 +612,140 @@ __global__ __launch_bounds__(1024, 8) void k_step_batch(StepArgs a) {
 }
 
 // ------------------------------------------------------------------------
+// AFPPA on the nonsmooth HOITV model (Section 4.3).  With the gradient of the
+// fidelity at f~^k in hand (ratio forward projection, back projection):
+//   primal  f^{k+1} = max(f~ - P (grad F(f~) + B1^T b~ + B2^T c~), 0),
+//           w = 2 f^{k+1} - f~, f~^{k+1} = f^{k+1} + theta_{k+1} (f^{k+1} - f^k),
+//           and the max over pixels of P = beta f^k / Lambda per solve;
+//   dual    rho1 = 1 / (2 * 8 * p_max), rho2 = 1 / (2 * 64 * p_max);
+//           b^{k+1} = rho1 (I - prox_{(lambda1/rho1)||.||})(b~ / rho1 + B1 w) per pixel
+//           group of 2 components, c^{k+1} likewise with rho2, lambda2 and the 4
+//           components of B2; b~^{k+1} = b^{k+1} + theta_{k+1} (b^{k+1} - b^k), c~ likewise.
+// With z' = b~ / rho + B1 w, (I - prox_{t||.||})(z') = z' min(1, t / ||z'||), so
+// b^{k+1} = z' min(rho, lambda / ||z'||): the dual kernel forms z' and this
+// scale, which stay finite when p_max is tiny (rho huge; an image driven to 0
+// by the EM preconditioner), where b~ + rho B1 w would overflow FP32.  One
+// thread per pixel and solve: for Bp == 1 a wave
+// covers 64 pixels, else a wave is one pixel and its lanes 64 solves.  The
+// stencils are those of the smoothed model's kernels: uv6 gives (B1 w, B2 w)
+// at a pixel, combine_grad gives B1^T p + B2^T q from the 6 components around it.
+// ------------------------------------------------------------------------
+
+template <bool LANES>
+struct AfppaIdx {
+    int d, b;
+    __device__ __forceinline__ size_t px(int j) const {        // element j of a d-vector
+        return LANES ? lidx(j, b, d) : static_cast<size_t>(j);
+    }
+    __device__ __forceinline__ size_t dual(int k, int j) const {  // component k at pixel j
+        return LANES ? lidx(k * d + j, b, 6 * d) : static_cast<size_t>(k) * d + j;
+    }
+};
+
+constexpr int kAfppaThreads = 1024;
+
+template <bool LANES>
+__global__ __launch_bounds__(kAfppaThreads) void k_afppa_primal(AfppaArgs a) {
+    constexpr int kWaves = kAfppaThreads / 64;
+    __shared__ float pmr[kWaves][64];
+    __shared__ double rer[kWaves][64][2];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int N = a.n, d = N * N;
+    const int j = LANES ? blockIdx.x * kWaves + w : blockIdx.x * kAfppaThreads + tid;
+    const int b = LANES ? blockIdx.y * 64 + lane : 0;
+    const bool in = j < d;
+    const AfppaIdx<LANES> ix{d, b};
+    float Pk = 0.0f;
+    double dd = 0.0, nn = 0.0;
+    if (in) {
+        const int r = j / N, c = j - r * N;
+        const size_t o = ix.px(j);
+        const LaneParams lp = a.lp[b];
+        const float fk = a.f[o], ftc = a.ft[o];
+        float gF = 0.0f;
+        const size_t stride = static_cast<size_t>(a.Bp) * d;
+        for (int q = 0; q < a.gf_split; ++q) gF += a.gf[q * stride + o];
+        auto Q = [&](int dr, int dc, int k) { return a.ybar[ix.dual(k, (r + dr) * N + (c + dc))]; };
+        const float gD = combine_grad(Q, r, c, N);
+        const float P = a.pmode == PM_FIXED ? lp.fixed_p : lp.beta * fk / a.lam[j];
+        const float z = ftc - P * (gF + gD);
+        const float fn = z > 0.0f ? z : 0.0f;
+        a.f[o] = fn;
+        a.w[o] = 2.0f * fn - ftc;
+        a.ft_next[o] = fn + a.theta_next[b] * (fn - fk);
+        Pk = fmaxf(P, 0.0f);
+        const double df = static_cast<double>(fn) - static_cast<double>(fk);
+        dd = df * df;
+        nn = static_cast<double>(fn) * static_cast<double>(fn);
+    }
+    if (!LANES) {   // one solve: reduce over the 64 pixels of the wave first
+        for (int sh = 32; sh >= 1; sh >>= 1) {
+            Pk = fmaxf(Pk, __shfl_xor(Pk, sh));
+            dd += __shfl_xor(dd, sh);
+            nn += __shfl_xor(nn, sh);
+        }
+    }
+    pmr[w][lane] = Pk;
+    rer[w][lane][0] = dd;
+    rer[w][lane][1] = nn;
+    __syncthreads();
+    if (w == 0 && (LANES || lane == 0)) {
+        float m = 0.0f;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            m = fmaxf(m, pmr[q][lane]);
+            s0 += rer[q][lane][0];
+            s1 += rer[q][lane][1];
+        }
+        if (a.pmode != PM_FIXED) atomicMax(&a.pmax_acc[b], __float_as_uint(m));
+        if (a.re_part) {
+            const size_t po = (static_cast<size_t>(blockIdx.x) * a.Bp + b) * 2;
+            a.re_part[po] = s0;
+            a.re_part[po + 1] = s1;
+        }
+    }
+}
+
+template <bool LANES>
+__global__ __launch_bounds__(kAfppaThreads) void k_afppa_dual(AfppaArgs a) {
+    constexpr int kWaves = kAfppaThreads / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int N = a.n, d = N * N;
+    const int j = LANES ? blockIdx.x * kWaves + w : blockIdx.x * kAfppaThreads + tid;
+    const int b = LANES ? blockIdx.y * 64 + lane : 0;
+    // the next iteration's max accumulator starts from 0 (its last reader, the
+    // dual kernel two iterations back, has finished)
+    if (blockIdx.x == 0 && (LANES ? w == 0 : tid == 0) && a.pmax_clear) a.pmax_clear[b] = 0u;
+    if (j >= d) return;
+    const AfppaIdx<LANES> ix{d, b};
+    const int r = j / N, c = j - r * N;
+    const LaneParams lp = a.lp[b];
+    const float pm = fmaxf(a.pmode == PM_FIXED ? lp.fixed_p : __uint_as_float(a.pmax_in[b]), 1e-30f);
+    const float irho1 = 16.0f * pm, irho2 = 128.0f * pm;   // 1 / rho1, 1 / rho2
+    auto W = [&](int rr, int cc) { return a.w[ix.px(rr * N + cc)]; };
+    float u[6];
+    uv6(W, r, c, N, u);
+    float z[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) z[k] = a.ybar[ix.dual(k, j)] * (k < 2 ? irho1 : irho2) + u[k];
+    const float n1 = sqrtf(z[0] * z[0] + z[1] * z[1]);
+    const float n2 = sqrtf(z[2] * z[2] + z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
+    // min(rho, lambda / ||z'||), compared as ||z'|| > lambda / rho
+    const float s1 = n1 > lp.lambda1 * irho1 ? lp.lambda1 / n1 : 1.0f / irho1;
+    const float s2 = n2 > lp.lambda2 * irho2 ? lp.lambda2 / n2 : 1.0f / irho2;
+    const float th = a.theta_next[b];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const size_t o = ix.dual(k, j);
+        const float yn = z[k] * (k < 2 ? s1 : s2);
+        const float yo = a.y[o];
+        a.y[o] = yn;
+        a.ybar[o] = yn + th * (yn - yo);
+    }
+}
+
+// ------------------------------------------------------------------------
 // Projections for B > 1 over tiles (Section 2.2: grad F = A^T e needs A x
 // and A^T e every iteration).
 //
@@ -971,8 +1105,9 @@ __global__ __launch_bounds__(256) void k_reg_value(int n, int B, int Bp, const f
             const double q2 = static_cast<double>(o[2]) * o[2] + static_cast<double>(o[3]) * o[3] +
                               static_cast<double>(o[4]) * o[4] + static_cast<double>(o[5]) * o[5];
             const double n1 = sqrt(q1), n2 = sqrt(q2);
-            const double s1 = n1 > eps ? n1 - eps / 2 : q1 / (2 * eps);
-            const double s2 = n2 > eps ? n2 - eps / 2 : q2 / (2 * eps);
+            // eps = 0 (the nonsmooth model) takes the first branch: the plain norm
+            const double s1 = n1 >= eps ? n1 - eps / 2 : q1 / (2 * eps);
+            const double s2 = n2 >= eps ? n2 - eps / 2 : q2 / (2 * eps);
             s += static_cast<double>(p.lambda1) * s1 + static_cast<double>(p.lambda2) * s2;
         }
     }
@@ -1232,6 +1367,29 @@ hipError_t launch_step(const DevCsr &AT, const StepArgs &args, int group, hipStr
     return by_type(AT.idx16, AT.vtype, [&](auto it, auto vt) {
         return step_dispatch<decltype(it), decltype(vt)::value>(args, group, st);
     });
+}
+
+int afppa_blocks(int n, int Bp) {
+    const int d = n * n;
+    return Bp == 1 ? (d + kAfppaThreads - 1) / kAfppaThreads : (d + kAfppaThreads / 64 - 1) / (kAfppaThreads / 64);
+}
+
+hipError_t launch_afppa_primal(const AfppaArgs &a, hipStream_t st) {
+    const dim3 grid(afppa_blocks(a.n, a.Bp), a.Bp == 1 ? 1 : a.Bp / 64);
+    if (a.Bp == 1)
+        hipLaunchKernelGGL(k_afppa_primal<false>, grid, dim3(kAfppaThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_afppa_primal<true>, grid, dim3(kAfppaThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_afppa_dual(const AfppaArgs &a, hipStream_t st) {
+    const dim3 grid(afppa_blocks(a.n, a.Bp), a.Bp == 1 ? 1 : a.Bp / 64);
+    if (a.Bp == 1)
+        hipLaunchKernelGGL(k_afppa_dual<false>, grid, dim3(kAfppaThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_afppa_dual<true>, grid, dim3(kAfppaThreads), 0, st, a);
+    return hipGetLastError();
 }
 
 int pad_lanes(int B) { return B == 1 ? 1 : (B + 63) / 64 * 64; }

@@ -1,0 +1,309 @@
+"""GPU parity of FPPA, AFPPA-N and AFPPA-GN on the nonsmooth HOITV model
+(Section 4.3): the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances:
+  * images: relative L2 <= max(1e-5, 4 x floor), where the floor is how far a
+    1e-7 relative perturbation of the data moves the FP64 oracle's result (the
+    problem's own sensitivity to FP32-size errors);
+  * duals (b, c): relative L2 <= max(1e-4, 40 x floor), or, where rho is large,
+    an error <= 1e-5 of rho1 ||B1 f||.  A dual group is the projection of
+    b~ + rho B1 w onto the lambda-ball (nonexpansive), so FP32 rounding of
+    that input, of size rho ||B1 w||, bounds its error; with a fixed P = 1/L,
+    rho1 = L / 16 makes that input ~1e4 times the dual.  Every group also stays
+    in its lambda-ball;
+  * objective: the reported Phi equals the oracle's nonsmooth objective of the
+    returned image to 1e-8 (FP64 reductions of an FP32 forward projection), and
+    the oracle's own Phi to 1e-7.
+"""
+import copy
+from concurrent.futures import ThreadPoolExecutor
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2409_13344_amd import appga as ap  # noqa: E402
+from paper_2409_13344_amd import synth  # noqa: E402
+
+LAM = 0.02
+K = 100
+# (name, momentum, omega, beta) of Section 4.3's comparison.  AFPPA-N runs with
+# beta = 1/2: with beta = 1 on this phantom its iterates blow up (max f ~ 6e12 by
+# k = 10) and the EM preconditioner then pins every pixel at 0, a state whose
+# duals are driven by rho ~ 1e28 and carry no information.
+VARIANTS = [("FPPA", ap.APPGA_MOMENTUM_NONE, 1.0, 1.0), ("AFPPA-N", ap.APPGA_MOMENTUM_NESTEROV, 1.0, 0.5),
+            ("AFPPA-GN 1/4", ap.APPGA_MOMENTUM_GN, 0.25, 1.0), ("AFPPA-GN 1/2", ap.APPGA_MOMENTUM_GN, 0.5, 1.0),
+            ("AFPPA-GN 3/4", ap.APPGA_MOMENTUM_GN, 0.75, 1.0), ("AFPPA-GN 1", ap.APPGA_MOMENTUM_GN, 1.0, 1.0)]
+OMOM = {ap.APPGA_MOMENTUM_NONE: oracle.MOMENTUM_NONE, ap.APPGA_MOMENTUM_NESTEROV: oracle.MOMENTUM_NESTEROV,
+        ap.APPGA_MOMENTUM_GN: oracle.MOMENTUM_GN}
+
+
+def say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def afppa_params(momentum, omega, iterations=K, lam=LAM, **kw):
+    return ap.make_params(lam=lam, omega=omega, momentum=momentum, iterations=iterations, **kw)
+
+
+def oracle_run(A, n, na, g, gam, momentum, omega, iterations, lam=LAM, **kw):
+    return oracle.afppa(A, n, na, np.asarray(g, np.float64), np.asarray(gam, np.float64), lam, lam,
+                        omega, iterations, momentum=OMOM[momentum], duals=True, history=True, **kw)
+
+
+def with_floor(A, n, na, g, gam, momentum, omega, iterations, seed, **kw):
+    """Oracle result, and the relative L2 moves of image and duals under a 1e-7
+    relative perturbation of the data."""
+    ref = oracle_run(A, n, na, g, gam, momentum, omega, iterations, **kw)
+    g64 = np.asarray(g, np.float64)
+    pert = g64 * (1.0 + 1e-7 * np.random.default_rng(seed).standard_normal(g64.shape))
+    rp = oracle_run(A, n, na, pert, gam, momentum, omega, iterations, **kw)
+    duals = np.concatenate([ref["b"], ref["c"]])
+    floor_f = rel_l2(rp["f"], ref["f"])
+    floor_y = rel_l2(np.concatenate([rp["b"], rp["c"]]), duals)
+    return ref, duals, floor_f, floor_y
+
+
+def check(name, f, duals, stats, ref, ref_duals, floor_f, floor_y, A, n, g, gam, lam=LAM):
+    e_f, e_y = rel_l2(f, ref["f"]), rel_l2(duals, ref_duals)
+    tol_f, tol_y = max(1e-5, 4.0 * floor_f), max(1e-4, 40.0 * floor_y)
+    # the dual error on the scale of the dual step's input rho1 B1 f
+    in_scale = ref["rho"][-1, 0] * np.linalg.norm(oracle.b1(n, ref["f"])) if len(ref["re"]) else 1.0
+    e_y_in = float(np.linalg.norm(np.asarray(duals, np.float64) - ref_duals)) / max(in_scale, 1e-300)
+    phi_img = oracle.objective_hoitv(A, n, np.asarray(g, np.float64), np.asarray(gam, np.float64),
+                                     lam, lam, f)
+    say("  %s: image %.2e (floor %.1e), duals %.2e (floor %.1e; %.1e of rho1 |B1 f|), Phi %.12e vs "
+        "%.12e, RE %.3e vs %.3e" % (name, e_f, floor_f, e_y, floor_y, e_y_in, stats["objective"],
+                                    ref["obj"][-1], stats["re"], ref["re"][-1]))
+    assert e_f <= tol_f, (name, e_f, tol_f)
+    assert e_y <= tol_y or e_y_in <= 1e-5, (name, e_y, tol_y, e_y_in)
+    assert f.min() >= 0.0
+    d = n * n
+    nb = np.linalg.norm(duals[:2 * d].reshape(2, d), axis=0)
+    nc = np.linalg.norm(duals[2 * d:].reshape(4, d), axis=0)
+    assert nb.max() <= lam * (1 + 1e-6) and nc.max() <= lam * (1 + 1e-6)
+    assert abs(stats["objective"] - phi_img) <= 1e-8 * abs(phi_img)
+    assert abs(stats["objective"] - ref["obj"][-1]) <= 1e-7 * abs(ref["obj"][-1])
+    assert abs(stats["objective0"] - ref["obj"][0]) <= 1e-7 * abs(ref["obj"][0])
+    assert stats["iterations_done"] == len(ref["re"])
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.init()
+    c = ap.appga_create(0)
+    yield c
+    ap.appga_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return synth.config_problem("c2_128")
+
+
+@pytest.fixture(scope="module")
+def c2_mat(ctx, c2):
+    m = ap.load_matrix(ctx, c2.A, c2.geom, "f32")
+    yield m
+    ap.appga_free_system_matrix(ctx, m)
+
+
+@pytest.fixture(scope="module")
+def c2_refs(c2):
+    """Oracle runs (with floors) of the six variants on the 128^2 configuration."""
+    say("AFPPA oracle runs, 128^2, %d iterations" % K)
+
+    def run(v):
+        _, mom, om, beta = v
+        return with_floor(c2.A, 128, 168, c2.g[0], c2.gamma[0], mom, om, K, seed=11, beta=beta)
+
+    with ThreadPoolExecutor(6) as ex:
+        return list(ex.map(run, VARIANTS))
+
+
+@pytest.mark.parametrize("vi", range(len(VARIANTS)))
+def test_single_solve_variants(ctx, c2, c2_mat, c2_refs, vi):
+    """B = 1 (the single-solve layout and kernels) against the oracle."""
+    name, mom, om, beta = VARIANTS[vi]
+    say("AFPPA single %s" % name)
+    d = c2.geom.d
+    f, du, st = ap.appga_afppa_batch(ctx, c2_mat, d, c2.g[:1], c2.gamma[:1],
+                                     [afppa_params(mom, om, beta=beta)], duals=True)
+    ref, ref_duals, floor_f, floor_y = c2_refs[vi]
+    check(name, f[0], du[0], st[0], ref, ref_duals, floor_f, floor_y, c2.A, 128, c2.g[0], c2.gamma[0])
+
+
+def test_batch_of_variants(ctx, c2, c2_mat, c2_refs):
+    """All six variants as one batch (lane layout, tile projections, per-solve momentum),
+    each against the oracle."""
+    say("AFPPA batch of the six variants")
+    d = c2.geom.d
+    B = len(VARIANTS)
+    g = np.repeat(c2.g[:1], B, axis=0)
+    gam = np.repeat(c2.gamma[:1], B, axis=0)
+    params = [afppa_params(mom, om, beta=beta) for _, mom, om, beta in VARIANTS]
+    f, du, st = ap.appga_afppa_batch(ctx, c2_mat, d, g, gam, params, duals=True)
+    for b, (name, _, _, _) in enumerate(VARIANTS):
+        ref, ref_duals, floor_f, floor_y = c2_refs[b]
+        check("batch " + name, f[b], du[b], st[b], ref, ref_duals, floor_f, floor_y, c2.A, 128,
+              c2.g[0], c2.gamma[0])
+
+
+@pytest.mark.parametrize("B", [1, 3])
+def test_fixed_preconditioner(ctx, B):
+    """P = fixed_p I (rho1 = 1 / (16 fixed_p), rho2 = 1 / (128 fixed_p)) on a ragged 37^2 image,
+    fixed_p = 1 / L with L = ||A||^2 max g / gamma^2 (a Lipschitz constant of grad F on f >= 0)."""
+    import scipy.sparse as sp
+    from scipy.sparse.linalg import svds
+    say("AFPPA fixed P, 37^2, B=%d" % B)
+    geom = synth.Geometry(37, 60, 31)
+    pr = synth.make_problem(geom, list(range(40, 40 + B)), tc=2e5, rf=0.1, A=synth.cached_matrix(geom))
+    S = sp.csr_matrix((pr.A.val, pr.A.col, pr.A.row_ptr), shape=(pr.A.n_rows, pr.A.n_cols))
+    norm2 = svds(S, k=1, return_singular_vectors=False)[0] ** 2
+    L = max(norm2 * float(np.max(pr.g[b].astype(np.float64) / pr.gamma[b].astype(np.float64) ** 2))
+            for b in range(B))
+    mat = ap.load_matrix(ctx, pr.A, geom, "f32")
+    try:
+        p = 1.0 / L
+        params = [afppa_params(ap.APPGA_MOMENTUM_GN, 0.5, iterations=60, precond=ap.APPGA_PRECOND_FIXED,
+                               fixed_p=p) for _ in range(B)]
+        f, du, st = ap.appga_afppa_batch(ctx, mat, geom.d, pr.g, pr.gamma, params, duals=True)
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    for b in range(B):
+        ref, ref_duals, floor_f, floor_y = with_floor(
+            pr.A, 37, 31, pr.g[b], pr.gamma[b], ap.APPGA_MOMENTUM_GN, 0.5, 60, seed=b,
+            precond=oracle.PRECOND_FIXED, fixed_p_scalar=float(np.float32(p)))
+        check("fixed P solve %d" % b, f[b], du[b], st[b], ref, ref_duals, floor_f, floor_y, pr.A, 37,
+              pr.g[b], pr.gamma[b])
+
+
+@pytest.mark.parametrize("B", [1, 3])
+def test_lambda_zero_equals_appga_on_gpu(ctx, c2, c2_mat, B):
+    """Without regularisation both solvers take the same projected EM-preconditioned
+    gradient step; the GPU results agree to FP32 rounding and the duals stay 0."""
+    say("AFPPA lambda = 0 vs APPGA, B=%d" % B)
+    d = c2.geom.d
+    g = np.repeat(c2.g[:1], B, axis=0)
+    gam = np.repeat(c2.gamma[:1], B, axis=0)
+    pa = [ap.make_params(lam=0.0, eps=1e-3, omega=0.5, iterations=40) for _ in range(B)]
+    pf = [afppa_params(ap.APPGA_MOMENTUM_GN, 0.5, iterations=40, lam=0.0) for _ in range(B)]
+    fa, _ = ap.appga_reconstruct_batch(ctx, c2_mat, d, g, gam, pa)
+    ff, du, _ = ap.appga_afppa_batch(ctx, c2_mat, d, g, gam, pf, duals=True)
+    for b in range(B):
+        e = rel_l2(ff[b], fa[b])
+        say("  solve %d: AFPPA vs APPGA %.3e (bit-equal: %s)" % (b, e, np.array_equal(ff[b], fa[b])))
+        assert e <= 1e-7
+    assert np.all(du == 0.0)
+
+
+@pytest.fixture(scope="module")
+def c2_pair(c2):
+    """Two sinograms on the 128^2 configuration's matrix."""
+    return synth.make_problem(c2.geom, [2, 3], tc=1e6, rf=0.1, A=c2.A)
+
+
+def test_zero_iterations(ctx, c2, c2_mat, c2_pair):
+    say("AFPPA zero iterations")
+    d = c2.geom.d
+    pr = c2_pair
+    f, du, st = ap.appga_afppa_batch(ctx, c2_mat, d, pr.g, pr.gamma,
+                                     [afppa_params(ap.APPGA_MOMENTUM_GN, 0.5, iterations=0)] * 2,
+                                     duals=True)
+    for b in range(2):
+        init = oracle.init_image(128, 168, pr.g[b], pr.gamma[b])
+        assert rel_l2(f[b], init) <= 1e-6
+        assert st[b]["iterations_done"] == 0
+    assert np.all(du == 0.0)
+
+
+def test_session_monitor_and_duals(ctx, c2, c2_mat, c2_pair):
+    """appga_afppa_begin / step / history / duals / end: the monitored nonsmooth
+    objective and the duals mid-run match the oracle."""
+    say("AFPPA session with monitor")
+    d = c2.geom.d
+    pr = c2_pair
+    B = 2
+    assert pr.g.shape == (B, c2.geom.m) and pr.gamma.shape == (B, c2.geom.m)
+    g_t = torch.as_tensor(np.ascontiguousarray(pr.g, np.float32)).cuda()
+    gam_t = torch.as_tensor(np.ascontiguousarray(pr.gamma, np.float32)).cuda()
+    params = [afppa_params(ap.APPGA_MOMENTUM_GN, 0.5, monitor_every=20) for _ in range(B)]
+    s = ap.appga_afppa_begin(ctx, c2_mat, g_t, gam_t, params)
+    for _ in range(3):
+        ap.appga_solve_step(s, 20)
+    du_t = torch.empty((B, 6 * d), dtype=torch.float32, device="cuda")
+    ap.appga_solve_duals(s, du_t)
+    hist = [ap.appga_solve_history(s, b) for b in range(B)]
+    out_t = torch.empty((B, d), dtype=torch.float32, device="cuda")
+    st = ap.appga_solve_end(s, out_t, B)
+    f, du = out_t.cpu().numpy(), du_t.cpu().numpy()
+    for b in range(B):
+        ref = oracle_run(c2.A, 128, 168, pr.g[b], pr.gamma[b], ap.APPGA_MOMENTUM_GN, 0.5, 60)
+        ks, obj = hist[b]
+        assert list(ks) == [1, 21, 41, 61]
+        err = np.abs(obj - ref["obj"][ks - 1]).max()
+        say("  solve %d: monitored Phi max diff %.3e (|Phi| %.3e), image %.2e, duals %.2e" % (
+            b, err, abs(ref["obj"][0]), rel_l2(f[b], ref["f"]),
+            rel_l2(du[b], np.concatenate([ref["b"], ref["c"]]))))
+        assert err <= 1e-7 * abs(ref["obj"][0])
+        assert rel_l2(f[b], ref["f"]) <= 1e-5
+        assert rel_l2(du[b], np.concatenate([ref["b"], ref["c"]])) <= 1e-4
+        assert st[b]["iterations_done"] == 60
+
+
+def test_batched_configuration_sampled(ctx):
+    """128^2 x 64 solves with the BF16 matrix (the batched configuration): sampled solves
+    against the oracle on the dequantised matrix."""
+    say("AFPPA C3 bf16 x 64, sampled")
+    pr = synth.config_problem("c3_128x64")
+    mat = ap.load_matrix(ctx, pr.A, pr.geom, "bf16")
+    try:
+        deq = ap.appga_matrix_dequantized(mat, pr.A.nnz)
+        params = [afppa_params(ap.APPGA_MOMENTUM_GN, 0.5)] * 64
+        f, du, st = ap.appga_afppa_batch(ctx, mat, pr.geom.d, pr.g, pr.gamma, params, duals=True)
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    Aq = copy.copy(pr.A)
+    Aq.val = deq
+
+    def run(b):
+        return with_floor(Aq, 128, 168, pr.g[b], pr.gamma[b], ap.APPGA_MOMENTUM_GN, 0.5, K, seed=b)
+
+    with ThreadPoolExecutor(3) as ex:
+        res = list(ex.map(run, (0, 37, 63)))
+    for b, (ref, ref_duals, floor_f, floor_y) in zip((0, 37, 63), res):
+        check("C3 solve %d" % b, f[b], du[b], st[b], ref, ref_duals, floor_f, floor_y, Aq, 128,
+              pr.g[b], pr.gamma[b])
+
+
+def test_afppa_errors_through_the_abi(ctx, c2, c2_mat):
+    say("AFPPA errors")
+    d = c2.geom.d
+    bad = afppa_params(ap.APPGA_MOMENTUM_GN, 0.5, precond=ap.APPGA_PRECOND_EM_FROZEN)
+    with pytest.raises(ap.AppgaError, match="EM or the fixed"):
+        ap.appga_afppa_batch(ctx, c2_mat, d, c2.g[:1], c2.gamma[:1], [bad])
+    nest = ap.make_params(lam=LAM, eps=1e-3, omega=1.0, momentum=ap.APPGA_MOMENTUM_NESTEROV, iterations=5)
+    with pytest.raises(ap.AppgaError, match="unknown momentum"):
+        ap.appga_reconstruct_batch(ctx, c2_mat, d, c2.g[:1], c2.gamma[:1], [nest])
+    g_t = torch.as_tensor(np.ascontiguousarray(c2.g[:1], np.float32)).cuda()
+    s = ap.appga_solve_begin(ctx, c2_mat, g_t, None, [ap.make_params(lam=LAM, eps=1e-3, gamma_scalar=1.0)])
+    try:
+        du_t = torch.empty(6 * d, dtype=torch.float32, device="cuda")
+        with pytest.raises(ap.AppgaError, match="not an AFPPA session"):
+            ap.appga_solve_duals(s, du_t)
+    finally:
+        out_t = torch.empty(d, dtype=torch.float32, device="cuda")
+        ap.appga_solve_end(s, out_t, 1)
