@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="bf16", choices=["f32", "bf16", "f16", "fp8"])
     ap.add_argument("--plain-steps", type=int, default=200)
+    ap.add_argument("--afppa-steps", type=int, default=200,
+                    help="timed AFPPA-GN steps on the same workload (0 = skip the leg)")
+    ap.add_argument("--afppa-cpu-iters", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2000)
     ap.add_argument("--profile", action="store_true",
@@ -102,8 +105,82 @@ def kernel_bytes(kind: str, nnz: int, m: int, d: int, B: int, s_val: int, s_idx:
     if kind == "update":
         # A^T e + ft + f read/write + ft_next (each d x B) + Lambda
         return 4 * B * 5 * d + 4 * d
+    if kind == "afppa_primal":
+        # A^T e + f read/write + ft + ft_next + w (each d x B), the 6 extrapolated dual
+        # components (6 d x B) read, Lambda
+        return 4 * B * 12 * d + 4 * d
+    if kind == "afppa_dual":
+        # w (d x B) read; duals and their extrapolation (6 d x B each) read and written
+        return 4 * B * 25 * d
     # fused step: transpose + row_ptr + e (m x B) + ft (d x B) + f read/write + ft_next + Lambda
     return nnz * (s_val + s_idx) + (d + 1) * 4 + 4 * B * (m + 4 * d) + 4 * d
+
+
+def afppa_leg(ap, torch, ctx, mat, pr, g_t, stream, args, s_val, s_idx):
+    """AFPPA-GN (Section 4.3, nonsmooth HOITV model) on the same 64 sinograms: the
+    same projections plus the primal and dual kernels per step."""
+    B, geom = len(pr.seeds), pr.geom
+    m, d, nnz = geom.m, geom.d, pr.A.nnz
+    params = [ap.make_params(lam=0.02, omega=0.5, iterations=300, momentum=ap.APPGA_MOMENTUM_GN,
+                             gamma_scalar=float(pr.gamma[b][0])) for b in range(B)]
+    sess = ap.appga_afppa_begin(ctx, mat, g_t, None, params, None, stream)
+    for _ in range(args.warmup):
+        ap.appga_solve_step(sess, 1)
+    torch.cuda.synchronize()
+    log("timing %d AFPPA-GN steps" % args.afppa_steps)
+    t0 = time.perf_counter()
+    for _ in range(args.afppa_steps):
+        ap.appga_solve_step(sess, 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ap.appga_set_kernel_timing(ctx, True)
+    for _ in range(max(10, min(args.afppa_steps, 100))):
+        ap.appga_solve_step(sess, 1)
+    torch.cuda.synchronize()
+    times = ap.appga_kernel_times(ctx)
+    ap.appga_set_kernel_timing(ctx, False)
+    out_t = torch.empty((B, d), dtype=torch.float32, device=g_t.device)
+    stats = ap.appga_solve_end(sess, out_t, B)
+    kernels = {}
+    for name, kind in (("fwd_tiles", "forward"), ("back_tiles", "back"), ("afppa_primal", "afppa_primal"),
+                       ("afppa_dual", "afppa_dual")):
+        t = times.get(name)
+        if not t or t["count"] == 0:
+            continue
+        avg_ms = t["total_ms"] / t["count"]
+        nbytes = kernel_bytes(kind, nnz, m, d, B, s_val, s_idx)
+        gbs = nbytes / (avg_ms * 1e-3) / 1e9
+        kernels[name] = dict(avg_us=round(1e3 * avg_ms, 2), bytes=nbytes, gbs=round(gbs, 1),
+                             hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+    return dict(value=round(B * args.afppa_steps / dt, 1), unit="solve-iterations/s",
+                ms_per_step=round(1e3 * dt / args.afppa_steps, 4), steps=args.afppa_steps,
+                method="AFPPA-GN, omega = 1/2, beta = 1, EM preconditioner, lambda1 = lambda2 = 0.02",
+                kernels=kernels, objective_lane0=stats[0]["objective"])
+
+
+def cpu_baseline_afppa(pr, n_iters: int):
+    """FP64 AFPPA oracle on the host cores (context for the AFPPA leg)."""
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16, len(pr.seeds)))
+    oracle.load()
+
+    def run(i):
+        oracle.afppa(pr.A, pr.geom.n, pr.geom.n_angles, pr.g[i], pr.gamma[i], 0.02, 0.02, 0.5, n_iters)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(cores)]
+    t0 = time.perf_counter()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    dt = time.perf_counter() - t0
+    return dict(value=round(cores * n_iters / dt, 1), unit="solve-iterations/s", cores=cores,
+                kind="oracle", sample="%d of the 64 sinograms x %d AFPPA-GN iterations, one solve per "
+                                      "thread, FP64, %.1f s wall" % (cores, n_iters, dt))
 
 
 def cpu_baseline(pr, n_iters: int):
@@ -300,6 +377,14 @@ def main():
                 kernel=dom, avg_us=round(kernels[dom]["avg_us"], 2),
                 bytes_per_launch=kernels[dom]["bytes"])
 
+    # ------------------------------------------- AFPPA on the same workload ---
+    afppa = None
+    if args.afppa_steps > 0:
+        afppa = afppa_leg(ap, torch, ctx, mat, pr, g_t, stream, args, s_val, s_idx)
+        if not args.no_cpu_baseline and not args.profile:
+            log("timing the FP64 AFPPA oracle on the host cores")
+            afppa["cpu_oracle"] = cpu_baseline_afppa(pr, args.afppa_cpu_iters)
+
     # ----------------------------------------------------- plain (B = 1) ---
     plain = None
     if not args.profile:
@@ -387,6 +472,7 @@ def main():
                         for kk, vv in v.items()} for k, v in kernels.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "afppa": afppa,
         "serving": serving,
         "projector_single_256": projector,
         "matrix_bytes": info,

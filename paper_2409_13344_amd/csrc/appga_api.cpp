@@ -882,7 +882,7 @@ static appga_status sess_alloc(appga_solve *s) {
     const size_t o_w = s->afppa ? take(sizeof(float) * d * Bp) : 0;
     const size_t o_y = s->afppa ? take(sizeof(float) * 6 * d * Bp) : 0;
     const size_t o_yb = s->afppa ? take(sizeof(float) * 6 * d * Bp) : 0;
-    const size_t o_pm = s->afppa ? take(sizeof(unsigned) * 3 * Bp) : 0;
+    const size_t o_pm = s->afppa ? take(sizeof(unsigned) * 3 * kAfppaPmSlots * Bp) : 0;
     const size_t n_tp = B > 1 && s->mat->ft.valid ? fwd_tile_part_floats(s->mat->ft, Bp) : 0;
     const size_t o_tp = n_tp ? take(sizeof(float) * n_tp) : 0;
     const size_t o_lp = take(sizeof(LaneParams) * Bp);
@@ -1055,7 +1055,8 @@ appga_status sess_begin(appga_ctx *ctx, const appga_matrix *mat, int B, const fl
     if (he == hipSuccess && afppa)
         he = launch_fill(s->ybar, static_cast<size_t>(6) * d * Bp, 0.0f, s->st);
     if (he == hipSuccess && afppa)
-        he = launch_fill(reinterpret_cast<float *>(s->pm), 3 * static_cast<size_t>(Bp), 0.0f, s->st);
+        he = launch_fill(reinterpret_cast<float *>(s->pm), static_cast<size_t>(3) * kAfppaPmSlots * Bp, 0.0f,
+                         s->st);
     // initial image f^0 = f^1
     if (he == hipSuccess) {
         if (d_f_init) {
@@ -1195,9 +1196,10 @@ static appga_status afppa_step(appga_solve *s, int n_iters) {
         aa.lp = s->lp;
         aa.theta_next = s->theta + static_cast<size_t>(k + 1 - s->theta_base) * Bp;
         aa.pmode = p0.precond == APPGA_PRECOND_FIXED ? PM_FIXED : PM_EM;
-        aa.pmax_acc = s->pm + static_cast<size_t>(k % 3) * Bp;
+        const size_t pm_set = static_cast<size_t>(kAfppaPmSlots) * Bp;
+        aa.pmax_acc = s->pm + static_cast<size_t>(k % 3) * pm_set;
         aa.pmax_in = aa.pmax_acc;
-        aa.pmax_clear = s->pm + static_cast<size_t>((k + 1) % 3) * Bp;
+        aa.pmax_clear = s->pm + static_cast<size_t>((k + 1) % 3) * pm_set;
         aa.re_part = (it == n_iters - 1) ? s->part : nullptr;
         HIP_TRY(timed_launch(s->ctx, "afppa_primal", s->st, [&] { return launch_afppa_primal(aa, s->st); }));
         HIP_TRY(timed_launch(s->ctx, "afppa_dual", s->st, [&] { return launch_afppa_dual(aa, s->st); }));

@@ -77,8 +77,8 @@ struct appga_solve {
     std::vector<double> hist_obj;   // [entry][B]
     std::chrono::steady_clock::time_point t0;
     // AFPPA sessions (Section 4.3): w = 2 f^{k+1} - f~, the duals (b, c) and their
-    // extrapolation as 6 components per pixel, and three rotating per-solve
-    // accumulators of max P (FP32 bits)
+    // extrapolation as 6 components per pixel, and three rotating sets of
+    // per-solve accumulators of max P (kAfppaPmSlots each, FP32 bits)
     bool afppa = false;
     float *w = nullptr, *ydual = nullptr, *ybar = nullptr;
     unsigned *pm = nullptr;

@@ -210,11 +210,16 @@ struct AfppaArgs {
     const LaneParams *lp;      // [Bp]
     const float *theta_next;   // [Bp] theta_{k+1}
     int pmode;                 // PM_EM or PM_FIXED
-    unsigned *pmax_acc;        // [Bp] primal: running max of P at f^k (FP32 bits of values >= 0)
-    const unsigned *pmax_in;   // [Bp] dual: the max the primal of this iteration accumulated
-    unsigned *pmax_clear;      // [Bp] dual: accumulator of the next iteration, set to 0 here
+    // max of P at f^k per solve as kAfppaPmSlots partial maxima [slot][Bp] (FP32 bits
+    // of values >= 0): the primal accumulates them, the dual reads them and clears
+    // the set of the next iteration
+    unsigned *pmax_acc;
+    const unsigned *pmax_in;
+    unsigned *pmax_clear;
     double *re_part;           // primal: [blocks][Bp][2] sum (f^{k+1} - f^k)^2, sum (f^{k+1})^2 (or null)
 };
+
+constexpr int kAfppaPmSlots = 32;
 
 // Workgroups of the AFPPA kernels (RE partial sums per workgroup).
 int afppa_blocks(int n, int Bp);

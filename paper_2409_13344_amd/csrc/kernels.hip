@@ -624,12 +624,34 @@ __global__ __launch_bounds__(1024, 8) void k_step_batch(StepArgs a) {
 // With z' = b~ / rho + B1 w, (I - prox_{t||.||})(z') = z' min(1, t / ||z'||), so
 // b^{k+1} = z' min(rho, lambda / ||z'||): the dual kernel forms z' and this
 // scale, which stay finite when p_max is tiny (rho huge; an image driven to 0
-// by the EM preconditioner), where b~ + rho B1 w would overflow FP32.  One
-// thread per pixel and solve: for Bp == 1 a wave
-// covers 64 pixels, else a wave is one pixel and its lanes 64 solves.  The
+// by the EM preconditioner), where b~ + rho B1 w would overflow FP32.  For
+// Bp == 1 a thread is a pixel (a wave covers 64); else a wave takes kAfppaPix
+// pixels in turn, its lanes the 64 solves of a chunk, and issues the loads of
+// all of them before the updates.  The
 // stencils are those of the smoothed model's kernels: uv6 gives (B1 w, B2 w)
-// at a pixel, combine_grad gives B1^T p + B2^T q from the 6 components around it.
+// at a pixel, combine_grad (here in its select-only form) gives B1^T p + B2^T q
+// from the 6 components around it.
 // ------------------------------------------------------------------------
+
+// B1^T p + B2^T q at (r, c) as combine_grad computes it, written with selects
+// only: Q must read values already in registers (every (dr, dc, k) it names
+// is evaluated), so no load is moved into a branch and all of them can be in
+// flight together.
+template <typename Qf>
+__device__ __forceinline__ float combine_grad_sel(const Qf &Q, int r, int c, int N) {
+    const bool cl = c >= 1, cr = c <= N - 2, ru = r >= 1, rd = r <= N - 2;
+    float g = (cl ? Q(0, 0, 0) : 0.0f) - (cr ? Q(0, 1, 0) : 0.0f);
+    g += (ru ? Q(0, 0, 1) : 0.0f) - (rd ? Q(1, 0, 1) : 0.0f);
+    g += (cr ? Q(0, 1, 2) - Q(0, 0, 2) : 0.0f) + (cl ? Q(0, -1, 2) - Q(0, 0, 2) : 0.0f);
+    const float t0 = (cl ? Q(0, 0, 3) : 0.0f) - (cr ? Q(0, 1, 3) : 0.0f);
+    const float t1 = (cl ? Q(-1, 0, 3) : 0.0f) - (cr ? Q(-1, 1, 3) : 0.0f);
+    g -= ru ? t0 - t1 : 0.0f;
+    g += (rd ? Q(1, 0, 4) - Q(0, 0, 4) : 0.0f) + (ru ? Q(-1, 0, 4) - Q(0, 0, 4) : 0.0f);
+    const float s0 = -(Q(0, 0, 5) - Q(0, -1, 5));
+    const float s1 = rd ? -(Q(1, 0, 5) - Q(1, -1, 5)) : 0.0f;
+    g += cl ? (ru ? s0 : 0.0f) - s1 : 0.0f;
+    return g;
+}
 
 template <bool LANES>
 struct AfppaIdx {
@@ -642,41 +664,73 @@ struct AfppaIdx {
     }
 };
 
-constexpr int kAfppaThreads = 1024;
+constexpr int kAfppaThreads = 256;
+constexpr int kAfppaPix = 4;   // pixels per wave in the lane layout (their loads in flight together)
 
-template <bool LANES>
+// SPLIT: the number of partial sums of A^T e (1 or 2, compile-time; 0 = a.gf_split)
+template <bool LANES, int SPLIT>
 __global__ __launch_bounds__(kAfppaThreads) void k_afppa_primal(AfppaArgs a) {
     constexpr int kWaves = kAfppaThreads / 64;
+    constexpr int NP = LANES ? kAfppaPix : 1;
     __shared__ float pmr[kWaves][64];
     __shared__ double rer[kWaves][64][2];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int N = a.n, d = N * N;
-    const int j = LANES ? blockIdx.x * kWaves + w : blockIdx.x * kAfppaThreads + tid;
+    const int j0 = LANES ? (blockIdx.x * kWaves + w) * NP : blockIdx.x * kAfppaThreads + tid;
     const int b = LANES ? blockIdx.y * 64 + lane : 0;
-    const bool in = j < d;
     const AfppaIdx<LANES> ix{d, b};
+    const LaneParams lp = a.lp[b];
+    const float th = a.theta_next[b];
+    const size_t stride = static_cast<size_t>(a.Bp) * d;
+    // loads of all NP pixels first, then the updates
+    // (pixels past the end of the image load pixel d - 1 and store nothing)
+    float fk[NP], ftc[NP], gF[NP], gD[NP], lam[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int j = min(j0 + p, d - 1);
+        {
+            const int r = j / N, c = j - r * N;
+            const size_t o = ix.px(j);
+            fk[p] = a.f[o];
+            ftc[p] = a.ft[o];
+            gF[p] = a.gf[o];
+            if (SPLIT == 2) gF[p] += a.gf[stride + o];
+            if (SPLIT == 0)
+                for (int q = 1; q < a.gf_split; ++q) gF[p] += a.gf[q * stride + o];
+            // the 3 x 3 neighbourhood of each component, loaded without branches at
+            // indices clamped into the image (combine_grad only uses in-image
+            // values; the loads it does not use are dropped by the compiler)
+            float v[6][3][3];
+            const int rr[3] = {max(r - 1, 0), r, min(r + 1, N - 1)};
+            const int cc[3] = {max(c - 1, 0), c, min(c + 1, N - 1)};
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+#pragma unroll
+                for (int u = 0; u < 3; ++u)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) v[k][u][t] = a.ybar[ix.dual(k, rr[u] * N + cc[t])];
+            auto Q = [&](int dr, int dc, int k) { return v[k][dr + 1][dc + 1]; };
+            gD[p] = combine_grad_sel(Q, r, c, N);
+            lam[p] = a.lam[j];
+        }
+    }
     float Pk = 0.0f;
     double dd = 0.0, nn = 0.0;
-    if (in) {
-        const int r = j / N, c = j - r * N;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int j = j0 + p;
+        if (j >= d) continue;
         const size_t o = ix.px(j);
-        const LaneParams lp = a.lp[b];
-        const float fk = a.f[o], ftc = a.ft[o];
-        float gF = 0.0f;
-        const size_t stride = static_cast<size_t>(a.Bp) * d;
-        for (int q = 0; q < a.gf_split; ++q) gF += a.gf[q * stride + o];
-        auto Q = [&](int dr, int dc, int k) { return a.ybar[ix.dual(k, (r + dr) * N + (c + dc))]; };
-        const float gD = combine_grad(Q, r, c, N);
-        const float P = a.pmode == PM_FIXED ? lp.fixed_p : lp.beta * fk / a.lam[j];
-        const float z = ftc - P * (gF + gD);
+        const float P = a.pmode == PM_FIXED ? lp.fixed_p : lp.beta * fk[p] / lam[p];
+        const float z = ftc[p] - P * (gF[p] + gD[p]);
         const float fn = z > 0.0f ? z : 0.0f;
         a.f[o] = fn;
-        a.w[o] = 2.0f * fn - ftc;
-        a.ft_next[o] = fn + a.theta_next[b] * (fn - fk);
-        Pk = fmaxf(P, 0.0f);
-        const double df = static_cast<double>(fn) - static_cast<double>(fk);
-        dd = df * df;
-        nn = static_cast<double>(fn) * static_cast<double>(fn);
+        a.w[o] = 2.0f * fn - ftc[p];
+        a.ft_next[o] = fn + th * (fn - fk[p]);
+        Pk = fmaxf(Pk, fmaxf(P, 0.0f));
+        const double df = static_cast<double>(fn) - static_cast<double>(fk[p]);
+        dd += df * df;
+        nn += static_cast<double>(fn) * static_cast<double>(fn);
     }
     if (!LANES) {   // one solve: reduce over the 64 pixels of the wave first
         for (int sh = 32; sh >= 1; sh >>= 1) {
@@ -698,7 +752,10 @@ __global__ __launch_bounds__(kAfppaThreads) void k_afppa_primal(AfppaArgs a) {
             s0 += rer[q][lane][0];
             s1 += rer[q][lane][1];
         }
-        if (a.pmode != PM_FIXED) atomicMax(&a.pmax_acc[b], __float_as_uint(m));
+        // one of kAfppaPmSlots accumulators per solve (by workgroup), so that the
+        // atomics of all workgroups do not queue on one cache line
+        if (a.pmode != PM_FIXED)
+            atomicMax(&a.pmax_acc[static_cast<size_t>(blockIdx.x % kAfppaPmSlots) * a.Bp + b], __float_as_uint(m));
         if (a.re_part) {
             const size_t po = (static_cast<size_t>(blockIdx.x) * a.Bp + b) * 2;
             a.re_part[po] = s0;
@@ -710,38 +767,73 @@ __global__ __launch_bounds__(kAfppaThreads) void k_afppa_primal(AfppaArgs a) {
 template <bool LANES>
 __global__ __launch_bounds__(kAfppaThreads) void k_afppa_dual(AfppaArgs a) {
     constexpr int kWaves = kAfppaThreads / 64;
+    constexpr int NP = LANES ? kAfppaPix : 1;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int N = a.n, d = N * N;
-    const int j = LANES ? blockIdx.x * kWaves + w : blockIdx.x * kAfppaThreads + tid;
+    const int j0 = LANES ? (blockIdx.x * kWaves + w) * NP : blockIdx.x * kAfppaThreads + tid;
     const int b = LANES ? blockIdx.y * 64 + lane : 0;
-    // the next iteration's max accumulator starts from 0 (its last reader, the
+    // the next iteration's max accumulators start from 0 (their last reader, the
     // dual kernel two iterations back, has finished)
-    if (blockIdx.x == 0 && (LANES ? w == 0 : tid == 0) && a.pmax_clear) a.pmax_clear[b] = 0u;
-    if (j >= d) return;
+    if (blockIdx.x == 0 && (LANES ? w == 0 : tid == 0) && a.pmax_clear)
+        for (int q = 0; q < kAfppaPmSlots; ++q) a.pmax_clear[static_cast<size_t>(q) * a.Bp + b] = 0u;
     const AfppaIdx<LANES> ix{d, b};
-    const int r = j / N, c = j - r * N;
     const LaneParams lp = a.lp[b];
-    const float pm = fmaxf(a.pmode == PM_FIXED ? lp.fixed_p : __uint_as_float(a.pmax_in[b]), 1e-30f);
-    const float irho1 = 16.0f * pm, irho2 = 128.0f * pm;   // 1 / rho1, 1 / rho2
-    auto W = [&](int rr, int cc) { return a.w[ix.px(rr * N + cc)]; };
-    float u[6];
-    uv6(W, r, c, N, u);
-    float z[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) z[k] = a.ybar[ix.dual(k, j)] * (k < 2 ? irho1 : irho2) + u[k];
-    const float n1 = sqrtf(z[0] * z[0] + z[1] * z[1]);
-    const float n2 = sqrtf(z[2] * z[2] + z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
-    // min(rho, lambda / ||z'||), compared as ||z'|| > lambda / rho
-    const float s1 = n1 > lp.lambda1 * irho1 ? lp.lambda1 / n1 : 1.0f / irho1;
-    const float s2 = n2 > lp.lambda2 * irho2 ? lp.lambda2 / n2 : 1.0f / irho2;
     const float th = a.theta_next[b];
+    // p_max of each solve: the first wave reduces the slots, the others read it from LDS
+    __shared__ float pm_lds[64];
+    if (w == 0) {
+        float pmx = 0.0f;
+        if (a.pmode != PM_FIXED)
+            for (int q = 0; q < kAfppaPmSlots; ++q)
+                pmx = fmaxf(pmx, __uint_as_float(a.pmax_in[static_cast<size_t>(q) * a.Bp + b]));
+        pm_lds[lane] = pmx;
+    }
+    __syncthreads();
+    const float pm = fmaxf(a.pmode == PM_FIXED ? lp.fixed_p : pm_lds[LANES ? lane : 0], 1e-30f);
+    const float irho1 = 16.0f * pm, irho2 = 128.0f * pm;   // 1 / rho1, 1 / rho2
+    // loads of all NP pixels first: z' = ybar / rho + (B1 w, B2 w), and the duals y^k
+    // (pixels past the end of the image load pixel d - 1 and store nothing)
+    float z[NP][6], yo[NP][6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const size_t o = ix.dual(k, j);
-        const float yn = z[k] * (k < 2 ? s1 : s2);
-        const float yo = a.y[o];
-        a.y[o] = yn;
-        a.ybar[o] = yn + th * (yn - yo);
+    for (int p = 0; p < NP; ++p) {
+        const int j = min(j0 + p, d - 1);
+        {
+            const int r = j / N, c = j - r * N;
+            // the 3 x 3 neighbourhood of w without branches (clamped indices; uv6
+            // only uses in-image values)
+            float wv[3][3];
+            const int rr[3] = {max(r - 1, 0), r, min(r + 1, N - 1)};
+            const int cc[3] = {max(c - 1, 0), c, min(c + 1, N - 1)};
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+#pragma unroll
+                for (int t = 0; t < 3; ++t) wv[u][t] = a.w[ix.px(rr[u] * N + cc[t])];
+            auto W = [&](int r2, int c2) { return wv[r2 - r + 1][c2 - c + 1]; };
+            float u[6];
+            uv6(W, r, c, N, u);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                z[p][k] = a.ybar[ix.dual(k, j)] * (k < 2 ? irho1 : irho2) + u[k];
+                yo[p][k] = a.y[ix.dual(k, j)];
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int j = j0 + p;
+        if (j >= d) continue;
+        const float n1 = sqrtf(z[p][0] * z[p][0] + z[p][1] * z[p][1]);
+        const float n2 = sqrtf(z[p][2] * z[p][2] + z[p][3] * z[p][3] + z[p][4] * z[p][4] + z[p][5] * z[p][5]);
+        // min(rho, lambda / ||z'||), compared as ||z'|| > lambda / rho
+        const float s1 = n1 > lp.lambda1 * irho1 ? lp.lambda1 / n1 : 1.0f / irho1;
+        const float s2 = n2 > lp.lambda2 * irho2 ? lp.lambda2 / n2 : 1.0f / irho2;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const size_t o = ix.dual(k, j);
+            const float yn = z[p][k] * (k < 2 ? s1 : s2);
+            a.y[o] = yn;
+            a.ybar[o] = yn + th * (yn - yo[p][k]);
+        }
     }
 }
 
@@ -1371,15 +1463,26 @@ hipError_t launch_step(const DevCsr &AT, const StepArgs &args, int group, hipStr
 
 int afppa_blocks(int n, int Bp) {
     const int d = n * n;
-    return Bp == 1 ? (d + kAfppaThreads - 1) / kAfppaThreads : (d + kAfppaThreads / 64 - 1) / (kAfppaThreads / 64);
+    const int per_block = Bp == 1 ? kAfppaThreads : (kAfppaThreads / 64) * kAfppaPix;
+    return (d + per_block - 1) / per_block;
 }
 
 hipError_t launch_afppa_primal(const AfppaArgs &a, hipStream_t st) {
     const dim3 grid(afppa_blocks(a.n, a.Bp), a.Bp == 1 ? 1 : a.Bp / 64);
-    if (a.Bp == 1)
-        hipLaunchKernelGGL(k_afppa_primal<false>, grid, dim3(kAfppaThreads), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_afppa_primal<true>, grid, dim3(kAfppaThreads), 0, st, a);
+    const dim3 block(kAfppaThreads);
+    if (a.gf_split < 1) return hipErrorInvalidValue;
+    if (a.Bp == 1) {
+        if (a.gf_split == 1)
+            hipLaunchKernelGGL((k_afppa_primal<false, 1>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_afppa_primal<false, 0>), grid, block, 0, st, a);
+    } else if (a.gf_split == 1) {
+        hipLaunchKernelGGL((k_afppa_primal<true, 1>), grid, block, 0, st, a);
+    } else if (a.gf_split == 2) {
+        hipLaunchKernelGGL((k_afppa_primal<true, 2>), grid, block, 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_afppa_primal<true, 0>), grid, block, 0, st, a);
+    }
     return hipGetLastError();
 }
 
