@@ -41,13 +41,15 @@ KERNELS_SRC = os.path.join(ROOT, "paper_2409_13344_amd", "csrc", "kernels.hip")
 # scaled by what the same counters read for a 1 GiB device copy (reads x2.00, writes
 # x1.00).  Valid only for the kernel source it was taken on (sha256 prefix below).
 MEASURED_TRAFFIC = {
-    "kernels_sha256_16": "ec46a76d445797e2",
+    "kernels_sha256_16": "9c0cbcbd76da6a13",
     "storage": "bf16",
     "read_scale": 2.0,
     "write_scale": 1.0,
-    "fwd_tiles": {"fetch_kib": 45998.2, "write_kib": 8556.4},
-    "back_tiles": {"fetch_kib": 28269.9, "write_kib": 8192.0},
-    "step_batch": {"fetch_kib": 8571.5, "write_kib": 9216.0},
+    "fwd_tiles": {"fetch_kib": 46002.0, "write_kib": 8558.8},
+    "back_tiles": {"fetch_kib": 28267.1, "write_kib": 8192.0},
+    "step_batch": {"fetch_kib": 10490.5, "write_kib": 9216.0},
+    "afppa_primal": {"fetch_kib": 21556.3, "write_kib": 13568.0},
+    "afppa_dual": {"fetch_kib": 27175.1, "write_kib": 49160.0},
 }
 
 
@@ -151,7 +153,8 @@ def afppa_leg(ap, torch, ctx, mat, pr, g_t, stream, args, s_val, s_idx):
         nbytes = kernel_bytes(kind, nnz, m, d, B, s_val, s_idx)
         gbs = nbytes / (avg_ms * 1e-3) / 1e9
         kernels[name] = dict(avg_us=round(1e3 * avg_ms, 2), bytes=nbytes, gbs=round(gbs, 1),
-                             hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+                             hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+                             traffic=measured_traffic(name, args.storage))
     return dict(value=round(B * args.afppa_steps / dt, 1), unit="solve-iterations/s",
                 ms_per_step=round(1e3 * dt / args.afppa_steps, 4), steps=args.afppa_steps,
                 method="AFPPA-GN, omega = 1/2, beta = 1, EM preconditioner, lambda1 = lambda2 = 0.02",

@@ -287,6 +287,9 @@ appga_status appga_solve_step(appga_solve *s, int32_t n_iters);
 appga_status appga_solve_history(const appga_solve *s, int32_t solve, int32_t cap, int32_t *iters_out,
                                  double *obj_out, int32_t *count);
 appga_status appga_solve_end(appga_solve *s, float *d_out, appga_stats *stats);
+/* The current image f^k of a session (either model) into d_out (device, B * d
+ * floats, solve-major); synchronises the session's stream.  The session goes on. */
+appga_status appga_solve_image(const appga_solve *s, float *d_out);
 /* An AFPPA session (same phases; the AFPPA parameter rules above; monitors and
  * stats give the nonsmooth objective). */
 appga_status appga_afppa_begin(appga_ctx *ctx, const appga_matrix *mat, int32_t B,

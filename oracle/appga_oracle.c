@@ -614,12 +614,18 @@ static void orc_ball_projection(double *z, int len, double t)
  * Section 2.1 already carries lambda1), so the ball radius is lambda/rho.
  * obj_hist (K+1): the nonsmooth objective at f^1 .. f^{K+1}; re_hist (K):
  * ||f^{k+1} - f^k|| / ||f^{k+1}||; rho_hist (2K): rho1, rho2 per step.
+ * round_f32: a diagnostic, not the method.  When nonzero, the quantities an
+ * FP32 implementation holds between its steps -- f~, b~, c~, A f~, e, grad F,
+ * B1^T b~ + B2^T c~, p_max, f^{k+1}, 2 f^{k+1} - f~, b^{k+1} and c^{k+1} -- are
+ * rounded to the nearest FP32 value each iteration, so that comparing the run
+ * with the exact one measures how much the run amplifies FP32-size
+ * perturbations injected at every iteration.
  */
 int orc_afppa(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, const double *val,
               int n_angles, const double *g, const double *gamma, double lambda1, double lambda2,
               double omega, double a, double b, double beta, int iterations, int momentum, int precond,
               double fixed_p_scalar, const double *f_init, double *f_out, double *b_out, double *c_out,
-              double *obj_hist, double *re_hist, double *rho_hist, int64_t *clamps)
+              double *obj_hist, double *re_hist, double *rho_hist, int64_t *clamps, int round_f32)
 {
     if (n <= 0 || m < 0 || iterations < 0 || !row_ptr || !g || !gamma || !f_out)
         return ORC_E_ARG;
@@ -665,12 +671,27 @@ int orc_afppa(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, cons
             bt[j] = bq[j] + theta * (bq[j] - bprev[j]);
         for (size_t j = 0; j < 4 * d; ++j)
             ct[j] = cq[j] + theta * (cq[j] - cprev[j]);
+        if (round_f32) {
+            for (size_t j = 0; j < d; ++j) ft[j] = (double)(float)ft[j];
+            for (size_t j = 0; j < 2 * d; ++j) bt[j] = (double)(float)bt[j];
+            for (size_t j = 0; j < 4 * d; ++j) ct[j] = (double)(float)ct[j];
+        }
         /* grad F at the extrapolated point */
         orc_forward(m, row_ptr, col, val, ft, y);
+        if (round_f32)
+            for (int64_t i = 0; i < m; ++i) y[i] = (double)(float)y[i];
         orc_ratio(m, y, g, gamma, e, &nclamp);
+        if (round_f32)
+            for (int64_t i = 0; i < m; ++i) e[i] = (double)(float)e[i];
         orc_back(m, (int64_t)d, row_ptr, col, val, e, gF);
         st = orc_b1t(n, bt, t1);
         if (st == ORC_OK) st = orc_b2t(n, ct, t2);
+        if (round_f32)
+            for (size_t j = 0; j < d; ++j) {
+                gF[j] = (double)(float)gF[j];
+                t1[j] = (double)(float)(t1[j] + t2[j]);
+                t2[j] = 0.0;
+            }
         /* preconditioner and the dual step sizes */
         double pmax = 0.0;
         for (size_t j = 0; j < d; ++j) {
@@ -678,6 +699,7 @@ int orc_afppa(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, cons
             if (p[j] > pmax) pmax = p[j];
         }
         if (pmax < 1e-30) pmax = 1e-30;
+        if (round_f32) pmax = (double)(float)pmax;
         double rho1 = 1.0 / (2.0 * 8.0 * pmax), rho2 = 1.0 / (2.0 * 64.0 * pmax);
         if (rho_hist) {
             rho_hist[2 * (k - 1)] = rho1;
@@ -687,7 +709,9 @@ int orc_afppa(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, cons
         for (size_t j = 0; j < d; ++j) {
             double z = ft[j] - p[j] * (gF[j] + t1[j] + t2[j]);
             fn[j] = z > 0.0 ? z : 0.0;
+            if (round_f32) fn[j] = (double)(float)fn[j];
             w[j] = 2.0 * fn[j] - ft[j];
+            if (round_f32) w[j] = (double)(float)w[j];
         }
         /* dual steps */
         if (st == ORC_OK) st = orc_b1(n, w, u);
@@ -705,6 +729,11 @@ int orc_afppa(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, cons
             orc_ball_projection(z2, 4, lambda2 / rho2);
             for (int c = 0; c < 4; ++c)
                 cq[c * d + i] = rho2 * z2[c];
+            if (round_f32) {
+                bq[i] = (double)(float)bq[i];
+                bq[d + i] = (double)(float)bq[d + i];
+                for (int c = 0; c < 4; ++c) cq[c * d + i] = (double)(float)cq[c * d + i];
+            }
         }
         if (re_hist) {
             double dn = 0.0, nn = 0.0;

@@ -84,7 +84,7 @@ def _declare(lib):
         "orc_hoitv_value": (I32, [I32, D, D, P, P]),
         "orc_objective_hoitv": (I32, [I32, I64, P, P, P, P, P, D, D, P, P]),
         "orc_afppa": (I32, [I32, I64, P, P, P, I32, P, P, D, D, D, D, D, D, I32, I32, I32, D, P, P, P, P,
-                            P, P, P, P]),
+                            P, P, P, P, I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -267,7 +267,7 @@ def objective_hoitv(A, n, g, gamma, lam1, lam2, f) -> float:
 
 def afppa(A, n, n_angles, g, gamma, lam1, lam2, omega, iterations, a=0.125, b=1.0, beta=1.0,
           momentum=MOMENTUM_GN, precond=PRECOND_EM, fixed_p_scalar=0.0, f_init=None, history=False,
-          duals=False):
+          duals=False, round_f32=False):
     """Run AFPPA (FPPA with momentum NONE, AFPPA-N with NESTEROV) in FP64 on the nonsmooth HOITV model.
 
     Returns dict(f=f^{K+1}, b, c (duals when asked), obj=[Phi_HOITV(f^1..f^{K+1})] or None,
@@ -287,7 +287,7 @@ def afppa(A, n, n_angles, g, gamma, lam1, lam2, omega, iterations, a=0.125, b=1.
     st = load().orc_afppa(n, A.n_rows, _ptr(rp), _ptr(col), _ptr(val), n_angles, _ptr(g), _ptr(gamma),
                           lam1, lam2, omega, a, b, beta, iterations, momentum, precond, fixed_p_scalar,
                           _ptr(fi), _ptr(f_out), _ptr(b_out), _ptr(c_out), _ptr(obj), _ptr(re), _ptr(rho),
-                          _ptr(cl))
+                          _ptr(cl), int(bool(round_f32)))
     _check(st, "afppa")
     return dict(f=f_out, b=b_out, c=c_out, obj=obj, re=re,
                 rho=None if rho is None else rho.reshape(iterations, 2), clamps=int(cl[0]))

@@ -88,6 +88,7 @@ _SIGS = {
     "appga_afppa_batch_device": [P, P, I32, P, P, C.POINTER(appga_params), P, P, P, P],
     "appga_afppa_begin": [P, P, I32, P, P, C.POINTER(appga_params), P, P, PP],
     "appga_solve_duals": [P, P],
+    "appga_solve_image": [P, P],
     "appga_solve_step": [P, I32],
     "appga_solve_end": [P, P, C.POINTER(appga_stats)],
     "appga_op_forward": [P, P, I32, P, P, P, P],
@@ -389,6 +390,14 @@ def appga_solve_duals(sess, duals_t) -> None:
         B, _, d = _SESS_DIMS[sess]
         _need(duals_t, B * 6 * d, "duals")
     _call("appga_solve_duals", sess, _ptr(duals_t))
+
+
+def appga_solve_image(sess, out_t) -> None:
+    """The session's current image f^k into out_t (B, d)."""
+    if sess in _SESS_DIMS:
+        B, _, d = _SESS_DIMS[sess]
+        _need(out_t, B * d, "out")
+    _call("appga_solve_image", sess, _ptr(out_t))
 
 
 def appga_solve_begin(ctx, mat, g_t, gamma_t, params: Sequence[appga_params], f_init_t=None,

@@ -1414,6 +1414,19 @@ appga_status sess_duals(const appga_solve *s, float *d_duals) {
     return APPGA_OK;
 }
 
+// The current image f^k of a session, solve-major [B][d].
+appga_status sess_image(const appga_solve *s, float *d_out) {
+    if (!s) return fail(APPGA_E_INVALID_ARG, "session is NULL");
+    if (!d_out) return fail(APPGA_E_INVALID_ARG, "NULL output");
+    const int64_t d = s->mat->A.n_cols;
+    if (s->Bp == 1)
+        HIP_TRY(hipMemcpyAsync(d_out, s->f, sizeof(float) * d, hipMemcpyDeviceToDevice, s->st));
+    else
+        HIP_TRY(launch_from_lanes(s->f, d_out, static_cast<int>(d), s->B, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    return APPGA_OK;
+}
+
 appga_status run_batch_device(appga_ctx *ctx, const appga_matrix *mat, int B, const float *d_g,
                               const float *d_gamma, const appga_params *params,
                               const float *d_f_init, float *d_out, hipStream_t st,
@@ -1558,6 +1571,11 @@ extern "C" appga_status appga_afppa_begin(appga_ctx *ctx, const appga_matrix *ma
 extern "C" appga_status appga_solve_duals(const appga_solve *s, float *d_duals) {
     clear_error();
     return sess_duals(s, d_duals);
+}
+
+extern "C" appga_status appga_solve_image(const appga_solve *s, float *d_out) {
+    clear_error();
+    return sess_image(s, d_out);
 }
 
 // ------------------------------------------------------------ operators ---

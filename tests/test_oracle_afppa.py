@@ -354,3 +354,26 @@ def test_afppa_rejects_bad_arguments(prob):
                 dict(precond=oracle.PRECOND_FIXED, fixed_p_scalar=0.0), dict(omega=1.0, a=0.5)):
         with pytest.raises(RuntimeError):
             oracle.afppa(**dict(base, **bad))
+
+
+def test_round_f32_diagnostic():
+    """The FP32-rounding diagnostic changes nothing where every held value is an FP32
+    number (A = I, integer counts, lambda = 0, no momentum: each iterate is g exactly and
+    the duals stay 0), and moves a real problem by an FP32-size amount."""
+    n = 4
+    d = n * n
+    A = synth.SparseMatrix(d, d, np.arange(d + 1, dtype=np.int64), np.arange(d, dtype=np.int32), np.ones(d))
+    g = np.random.default_rng(12).integers(1, 50, d).astype(np.float64)
+    kw = dict(momentum=oracle.MOMENTUM_NONE, f_init=np.full(d, 2.0), duals=True)
+    exact = oracle.afppa(A, n, 1, g, np.zeros(d), 0.0, 0.0, 1.0, 5, **kw)
+    rounded = oracle.afppa(A, n, 1, g, np.zeros(d), 0.0, 0.0, 1.0, 5, round_f32=True, **kw)
+    np.testing.assert_array_equal(exact["f"], rounded["f"])
+    np.testing.assert_array_equal(exact["f"], g)
+    pr = synth.config_problem("c1_64")
+    args = (pr.A, 64, 90, pr.g[0], pr.gamma[0], 0.05, 0.05, 0.5, 10)
+    f0 = oracle.afppa(*args, duals=True)
+    f1 = oracle.afppa(*args, duals=True, round_f32=True)
+    gap = np.linalg.norm(f1["f"] - f0["f"]) / np.linalg.norm(f0["f"])
+    assert 1e-9 < gap < 1e-5
+    assert np.abs(f1["f"] - f1["f"].astype(np.float32)).max() == 0.0
+    assert np.abs(f1["b"] - f1["b"].astype(np.float32)).max() == 0.0

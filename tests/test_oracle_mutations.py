@@ -66,8 +66,17 @@ AFPPA_MUTATIONS = {
     "afppa_dual_sign": ("z2[c] = ct[c * d + i] / rho2 + v[c * d + i];",
                         "z2[c] = ct[c * d + i] / rho2 - v[c * d + i];"),
     "afppa_dual_scale": ("bq[d + i] = rho1 * z1[1];", "bq[d + i] = z1[1];"),
-    "afppa_gradient_at_f": ("orc_forward(m, row_ptr, col, val, ft, y);\n        orc_ratio(m, y, g, gamma, e, &nclamp);\n        orc_back(m, (int64_t)d, row_ptr, col, val, e, gF);\n        st = orc_b1t",
-                            "orc_forward(m, row_ptr, col, val, f, y);\n        orc_ratio(m, y, g, gamma, e, &nclamp);\n        orc_back(m, (int64_t)d, row_ptr, col, val, e, gF);\n        st = orc_b1t"),
+    "afppa_gradient_at_f": ("orc_forward(m, row_ptr, col, val, ft, y);\n        if (round_f32)\n"
+                            "            for (int64_t i = 0; i < m; ++i) y[i] = (double)(float)y[i];\n"
+                            "        orc_ratio(m, y, g, gamma, e, &nclamp);\n        if (round_f32)\n"
+                            "            for (int64_t i = 0; i < m; ++i) e[i] = (double)(float)e[i];\n"
+                            "        orc_back(m, (int64_t)d, row_ptr, col, val, e, gF);\n        st = orc_b1t",
+                            "orc_forward(m, row_ptr, col, val, f, y);\n        if (round_f32)\n"
+                            "            for (int64_t i = 0; i < m; ++i) y[i] = (double)(float)y[i];\n"
+                            "        orc_ratio(m, y, g, gamma, e, &nclamp);\n        if (round_f32)\n"
+                            "            for (int64_t i = 0; i < m; ++i) e[i] = (double)(float)e[i];\n"
+                            "        orc_back(m, (int64_t)d, row_ptr, col, val, e, gF);\n        st = orc_b1t"),
+    "afppa_adjoint_of_unextrapolated_dual": ("st = orc_b1t(n, bt, t1);", "st = orc_b1t(n, bq, t1);"),
     "nesterov_recurrence": ("t = (1.0 + sqrt(1.0 + 4.0 * t * t)) / 2.0;",
                             "t = (1.0 + sqrt(1.0 + 2.0 * t * t)) / 2.0;"),
     "hoitv_group": ("s1 += sqrt(u[i] * u[i] + u[d + i] * u[d + i]);",
