@@ -756,3 +756,60 @@ int orc_afppa(int n, int64_t m, const int64_t *row_ptr, const int32_t *col, cons
     free(buf);
     return st;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Factored forward model (Section 4.1 simulation set-up): a space-invariant */
+/* Gaussian PSF H in image space and per-ray attenuation factors, so that   */
+/* A = diag(n) G H for a geometric projector G.                             */
+/* ------------------------------------------------------------------------ */
+
+/* Taps w[0..2R] of the 1-D Gaussian of full width at half maximum `fwhm`
+ * (in pixels), sigma = fwhm / (2 sqrt(2 ln 2)), at offsets -R..R, normalised
+ * to sum 1 over those 2R + 1 offsets. */
+int orc_psf_taps(double fwhm, int R, double *w)
+{
+    if (!w || R < 0 || !(fwhm > 0.0)) return ORC_E_DOMAIN;
+    double sigma = fwhm / (2.0 * sqrt(2.0 * log(2.0)));
+    double s = 0.0;
+    for (int t = -R; t <= R; ++t) {
+        w[t + R] = exp(-(double)t * t / (2.0 * sigma * sigma));
+        s += w[t + R];
+    }
+    for (int t = 0; t <= 2 * R; ++t)
+        w[t] /= s;
+    return ORC_OK;
+}
+
+/* out = H x for the n x n image x: out(r, c) = sum_{|a|,|b| <= R} w[a] w[b] x(r + a, c + b),
+ * where positions outside the image contribute 0 (so H is symmetric). */
+int orc_psf_apply(int n, int R, const double *w, const double *x, double *out)
+{
+    if (n <= 0 || R < 0 || !w || !x || !out) return ORC_E_ARG;
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) {
+            double s = 0.0;
+            for (int a = -R; a <= R; ++a) {
+                int rr = r + a;
+                if (rr < 0 || rr >= n) continue;
+                for (int b = -R; b <= R; ++b) {
+                    int cc = c + b;
+                    if (cc < 0 || cc >= n) continue;
+                    s += w[a + R] * w[b + R] * x[(size_t)rr * n + cc];
+                }
+            }
+            out[(size_t)r * n + c] = s;
+        }
+    return ORC_OK;
+}
+
+/* Attenuation factor of every ray: n_i = exp(-(G mu)_i), mu the attenuation
+ * coefficient per pixel in units of the projector's path lengths. */
+int orc_attenuation(int64_t m, const int64_t *row_ptr, const int32_t *col, const double *val,
+                    const double *mu, double *out)
+{
+    if (m < 0 || !row_ptr || !mu || !out) return ORC_E_ARG;
+    orc_forward(m, row_ptr, col, val, mu, out);
+    for (int64_t i = 0; i < m; ++i)
+        out[i] = exp(-out[i]);
+    return ORC_OK;
+}

@@ -18,7 +18,8 @@ __all__ = [
     "build_oracle", "load", "forward", "back", "b1", "b2", "b1t", "b2t", "s_eps", "reg_value",
     "grad_reg", "grad_fidelity", "objective", "em_lambda", "init_image", "theta", "appga",
     "t_nesterov", "theta_nesterov", "hoitv_value", "objective_hoitv", "afppa",
-    "MOMENTUM_GN", "MOMENTUM_NONE", "MOMENTUM_NESTEROV", "PRECOND_EM", "PRECOND_EM_FROZEN", "PRECOND_FIXED",
+    "MOMENTUM_GN", "MOMENTUM_NONE", "MOMENTUM_NESTEROV", "psf_radius", "psf_taps", "psf_apply",
+    "attenuation", "factored_matrix", "PRECOND_EM", "PRECOND_EM_FROZEN", "PRECOND_FIXED",
 ]
 
 MOMENTUM_GN, MOMENTUM_NONE, MOMENTUM_NESTEROV = 0, 1, 2
@@ -85,6 +86,9 @@ def _declare(lib):
         "orc_objective_hoitv": (I32, [I32, I64, P, P, P, P, P, D, D, P, P]),
         "orc_afppa": (I32, [I32, I64, P, P, P, I32, P, P, D, D, D, D, D, D, I32, I32, I32, D, P, P, P, P,
                             P, P, P, P, I32]),
+        "orc_psf_taps": (I32, [D, I32, P]),
+        "orc_psf_apply": (I32, [I32, I32, P, P, P]),
+        "orc_attenuation": (I32, [I64, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -291,3 +295,59 @@ def afppa(A, n, n_angles, g, gamma, lam1, lam2, omega, iterations, a=0.125, b=1.
     _check(st, "afppa")
     return dict(f=f_out, b=b_out, c=c_out, obj=obj, re=re,
                 rho=None if rho is None else rho.reshape(iterations, 2), clamps=int(cl[0]))
+
+
+# ------------------------------------------------------------- factored model ---
+
+def psf_radius(fwhm: float) -> int:
+    """Half-width R of the truncated Gaussian PSF: ceil(3 sigma), sigma = FWHM / (2 sqrt(2 ln 2))."""
+    import math
+    return int(math.ceil(3.0 * fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0)))))
+
+
+def psf_taps(fwhm: float, R: Optional[int] = None) -> np.ndarray:
+    """The 2R + 1 normalised Gaussian taps (Section 4.1's space-invariant PSF)."""
+    R = psf_radius(fwhm) if R is None else R
+    w = np.empty(2 * R + 1)
+    _check(load().orc_psf_taps(fwhm, R, _ptr(w)), "psf_taps")
+    return w
+
+
+def psf_apply(n: int, fwhm: float, x, R: Optional[int] = None) -> np.ndarray:
+    """H x: the 2-D Gaussian blur of the n x n image x (zero outside the image)."""
+    w = psf_taps(fwhm, R)
+    x = _f64(x)
+    out = np.empty(n * n)
+    _check(load().orc_psf_apply(n, (len(w) - 1) // 2, _ptr(w), _ptr(x), _ptr(out)), "psf_apply")
+    return out
+
+
+def attenuation(A, mu) -> np.ndarray:
+    """Per-ray attenuation factors exp(-(A mu)_i)."""
+    rp, col, val = _csr(A)
+    mu = _f64(mu)
+    out = np.empty(A.n_rows)
+    _check(load().orc_attenuation(A.n_rows, _ptr(rp), _ptr(col), _ptr(val), _ptr(mu), _ptr(out)),
+           "attenuation")
+    return out
+
+
+def factored_matrix(G, n: int, fwhm: float, factors=None):
+    """The explicit A = diag(factors) G H (a SparseMatrix) for small images: H is formed
+    column by column with psf_apply on unit vectors, then multiplied out with scipy."""
+    import scipy.sparse as sp
+    d = n * n
+    cols = []
+    for j in range(d):
+        e = np.zeros(d)
+        e[j] = 1.0
+        cols.append(sp.csc_matrix(psf_apply(n, fwhm, e).reshape(d, 1)))
+    H = sp.hstack(cols).tocsr()
+    Gs = sp.csr_matrix((G.val, G.col, G.row_ptr), shape=(G.n_rows, G.n_cols))
+    if factors is not None:
+        Gs = sp.diags(_f64(factors)) @ Gs
+    A = (Gs @ H).tocsr()
+    A.eliminate_zeros()
+    A.sort_indices()
+    return type(G)(A.shape[0], A.shape[1], A.indptr.astype(np.int64), A.indices.astype(np.int32),
+                   A.data.astype(np.float64))

@@ -19,6 +19,10 @@ attenuation, scatter) is not reproducible here, so the stand-in is:
 * phantom: random ellipses inside the field-of-view disk of radius N/2;
 * counts: total expected counts TC = sum(A f_true + gamma), a fraction r of
   them uniform background (the TC and RF definitions of Section 4.1).
+
+make_physics_problem adds the physics of Section 4.1's simulation on the same
+geometry: a space-invariant Gaussian PSF, uniform water attenuation, scatter
+and randoms (see its docstring).
 """
 from __future__ import annotations
 
@@ -30,7 +34,8 @@ import numpy as np
 
 __all__ = [
     "Geometry", "SparseMatrix", "Problem", "siddon_matrix", "ellipse_phantom", "disc_phantom",
-    "make_problem", "config_problem", "CONFIGS", "chord_length_square",
+    "make_problem", "config_problem", "CONFIGS", "chord_length_square", "PhysicsProblem",
+    "water_disc_mu", "make_physics_problem",
 ]
 
 
@@ -299,3 +304,88 @@ def config_problem(name: str, n_slices: Optional[int] = None) -> Problem:
     return make_problem(cfg["geom"], seeds, tc=cfg.get("tc", 1e6), rf=cfg.get("rf", 0.1),
                         A=cached_matrix(cfg["geom"]), tc_range=cfg.get("tc_range"),
                         rf_range=cfg.get("rf_range"))
+
+
+# ------------------------------------------------------- Section 4.1 physics ---
+
+@dataclasses.dataclass
+class PhysicsProblem:
+    """Data with PSF, attenuation, scatter and randoms.  The reconstruction model
+    is A = diag(att) G H with G = the Siddon matrix, H the Gaussian PSF of
+    `fwhm_px`, att the per-ray attenuation factors, and gamma = scatter + randoms."""
+    geom: Geometry
+    G: SparseMatrix
+    att: np.ndarray      # (m,) attenuation factors exp(-(G mu)_i), FP64
+    mu: np.ndarray       # (d,) attenuation coefficient per pixel (per unit path length)
+    fwhm_px: float
+    g: np.ndarray        # (B, m) float32 counts
+    gamma: np.ndarray    # (B, m) float32 scatter + randoms
+    f_true: np.ndarray   # (B, d) unblurred truth
+    tc: np.ndarray
+    seeds: List[int]
+
+
+def water_disc_mu(geom: Geometry, mu_per_cm: float = 0.096, fov_mm: float = 300.0) -> np.ndarray:
+    """Uniform water (0.096 / cm, Section 4.1) on the field-of-view disk of radius N/2, in
+    units of the geometry's pixel side (a pixel is fov_mm / N wide)."""
+    n = geom.n
+    c = np.arange(n) - (n - 1) / 2.0
+    y, x = np.meshgrid(c, c, indexing="ij")
+    inside = (x * x + y * y) <= (n / 2.0) ** 2
+    return np.where(inside, mu_per_cm * (fov_mm / n) / 10.0, 0.0).ravel()
+
+
+def make_physics_problem(geom: Geometry, seeds: List[int], tc=1e6, sf=0.25, rf=0.25,
+                         fwhm_mm=6.59, fov_mm=300.0, scatter_fwhm_px=None,
+                         G: Optional[SparseMatrix] = None, phantom: str = "ellipses") -> PhysicsProblem:
+    """Counts after Section 4.1's simulation recipe, per seed:
+
+    * the truth (random ellipses) blurred by the Gaussian PSF (FWHM fwhm_mm, pixel
+      fov_mm / N; scipy.ndimage.gaussian_filter, zero outside the image, truncated at 3
+      sigma) and forward projected through G, then attenuated: Tc = att * G (PSF f);
+    * scatter: the projection of a heavily smoothed truth (FWHM N/4 pixels), scaled so
+      that SF = Sc / (Tc + Sc);
+    * randoms: uniform, scaled so that RF = Rc / (Tc + Sc + Rc);
+    * everything scaled so that TC = Tc + Sc + Rc; g = Poisson(Tc + Sc + Rc).
+    The attenuation map is a water disc over the field of view, the same for every seed
+    (so a batch shares one system matrix).
+    """
+    from scipy.ndimage import gaussian_filter
+    if G is None:
+        G = siddon_matrix(geom)
+    m, d, n = geom.m, geom.d, geom.n
+    rows = np.repeat(np.arange(m), np.diff(G.row_ptr))
+
+    def project(x):
+        out = np.zeros(m)
+        np.add.at(out, rows, G.val * x[G.col])
+        return out
+
+    mu = water_disc_mu(geom, fov_mm=fov_mm)
+    att = np.exp(-project(mu))
+    fwhm_px = fwhm_mm / (fov_mm / n)
+    to_sigma = 1.0 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    s_fwhm = n / 4.0 if scatter_fwhm_px is None else scatter_fwhm_px
+    B = len(seeds)
+    g = np.zeros((B, m), dtype=np.float32)
+    gam = np.zeros((B, m), dtype=np.float32)
+    ftrue = np.zeros((B, d))
+    for k, seed in enumerate(seeds):
+        rng = np.random.default_rng(seed)
+        f0 = ellipse_phantom(n, rng) if phantom == "ellipses" else disc_phantom(n, rng)
+        img = f0.reshape(n, n)
+        blurred = gaussian_filter(img, fwhm_px * to_sigma, mode="constant", truncate=3.0).ravel()
+        smooth = gaussian_filter(img, s_fwhm * to_sigma, mode="constant", truncate=3.0).ravel()
+        T = att * project(blurred)
+        S = project(smooth)
+        S *= (sf / (1.0 - sf)) * T.sum() / S.sum()
+        Rc = (rf / (1.0 - rf)) * (T.sum() + S.sum())
+        R = np.full(m, Rc / m)
+        scale = tc / (T.sum() + S.sum() + R.sum())
+        f0 = f0 * scale
+        T, S, R = T * scale, S * scale, R * scale
+        noise = np.random.default_rng(seed + 10 ** 6)
+        g[k] = noise.poisson(T + S + R).astype(np.float32)
+        gam[k] = (S + R).astype(np.float32)
+        ftrue[k] = f0
+    return PhysicsProblem(geom, G, att, mu, fwhm_px, g, gam, ftrue, np.full(B, float(tc)), list(seeds))

@@ -84,16 +84,27 @@ AFPPA_MUTATIONS = {
 }
 
 
+# Mistakes in the factored forward model (PSF taps, blur, attenuation).
+FACTORED_MUTATIONS = {
+    "psf_sigma": ("double sigma = fwhm / (2.0 * sqrt(2.0 * log(2.0)));",
+                  "double sigma = fwhm / (2.0 * sqrt(log(2.0)));"),
+    "psf_unnormalised": ("w[t] /= s;", "w[t] /= 1.0;"),
+    "psf_clamped_border": ("if (rr < 0 || rr >= n) continue;", "if (rr < 0 || rr >= n) rr = rr < 0 ? 0 : n - 1;"),
+    "attenuation_sign": ("out[i] = exp(-out[i]);", "out[i] = exp(out[i]);"),
+}
+
+
 def _cases():
     return [(n, "test_oracle_pins.py") for n in sorted(MUTATIONS)] + \
-        [(n, "test_oracle_afppa.py") for n in sorted(AFPPA_MUTATIONS)]
+        [(n, "test_oracle_afppa.py") for n in sorted(AFPPA_MUTATIONS)] + \
+        [(n, "test_oracle_factored.py") for n in sorted(FACTORED_MUTATIONS)]
 
 
 @pytest.mark.slow
 @pytest.mark.parametrize("name,pins", _cases())
 def test_pins_catch_planted_mistake(name, pins, tmp_path):
     src = open(SRC).read()
-    old, new = dict(MUTATIONS, **AFPPA_MUTATIONS)[name]
+    old, new = dict(MUTATIONS, **AFPPA_MUTATIONS, **FACTORED_MUTATIONS)[name]
     assert src.count(old) >= 1, "mutation site not found: " + name
     c_file = tmp_path / (name + ".c")
     so_file = tmp_path / (name + ".so")
