@@ -133,6 +133,27 @@ appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geometry *geom
                                       const int64_t *row_ptr, const int32_t *col_idx,
                                       const double *values, appga_dtype storage,
                                       appga_matrix **out);
+/* Factored forward model (the physics of Section 4.1's simulation): the system
+ * is A = diag(row_factors) G H, where G is the matrix given as for
+ * appga_load_system_matrix, row_factors (m doubles, finite, >= 0, or NULL for
+ * 1) are per-ray factors such as the attenuation exp(-(G mu)_i), and H is a
+ * space-invariant Gaussian PSF of full width at half maximum psf_fwhm_px
+ * pixels (0 = none, at most 24).  H has taps w_t = exp(-t^2 / (2 sigma^2)) at
+ * offsets |t| <= R = ceil(3 sigma), sigma = FWHM / (2 sqrt(2 ln 2)), normalised
+ * to sum 1, applied along rows and columns with zero outside the image (so H
+ * is symmetric).  The row factors are folded into the stored values; Lambda
+ * = A^T 1 = H (G^T n).  Sessions of both models (appga_solve_*, appga_afppa_*,
+ * appga_reconstruct*) then project H f~ and back-project H (A^T e);
+ * appga_op_forward / appga_op_ratio / appga_op_back apply the whole A;
+ * appga_op_step and the server (appga_submit) return APPGA_E_INVALID_ARG for
+ * a matrix with a PSF.  Scatter and randoms enter as the background gamma. */
+appga_status appga_load_system_matrix_factored(appga_ctx *ctx, const appga_geometry *geom, int64_t nnz,
+                                               const int64_t *row_ptr, const int32_t *col_idx,
+                                               const double *values, appga_dtype storage,
+                                               const double *row_factors, double psf_fwhm_px,
+                                               appga_matrix **out);
+/* The PSF of a loaded matrix: *fwhm_px (0 when none) and the tap radius *radius (-1 when none). */
+appga_status appga_matrix_psf(const appga_matrix *mat, double *fwhm_px, int32_t *radius);
 appga_status appga_free_system_matrix(appga_ctx *ctx, appga_matrix *mat);
 
 /* Matrix facts: nnz, stored bytes of A and A^T (values + indices + row

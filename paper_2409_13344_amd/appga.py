@@ -76,6 +76,8 @@ _SIGS = {
     "appga_destroy": [P],
     "appga_load_system_matrix": [P, C.POINTER(appga_geometry), I64, P, P, P, C.c_int, PP],
     "appga_free_system_matrix": [P, P],
+    "appga_load_system_matrix_factored": [P, C.POINTER(appga_geometry), I64, P, P, P, C.c_int, P, D, PP],
+    "appga_matrix_psf": [P, C.POINTER(D), C.POINTER(I32)],
     "appga_matrix_info": [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I32)],
     "appga_matrix_dequantized": [P, P],
     "appga_reconstruct": [P, P, P, P, C.POINTER(appga_params), P, P, C.POINTER(appga_stats)],
@@ -242,6 +244,28 @@ def appga_load_system_matrix(ctx, n, n_angles, n_bins, row_ptr, col, val, storag
           DTYPES.get(storage, storage), C.byref(h))
     _MAT_DIMS[h.value] = (n_angles * n_bins, n * n)
     return h.value
+
+
+def appga_load_system_matrix_factored(ctx, n, n_angles, n_bins, row_ptr, col, val, storage="f32",
+                                      row_factors=None, psf_fwhm_px=0.0) -> int:
+    """A = diag(row_factors) G H (G the given CSR, H a Gaussian PSF of psf_fwhm_px pixels)."""
+    geom = appga_geometry(n, n_angles, n_bins)
+    rp, cl, vl = _np(row_ptr, np.int64), _np(col, np.int32), _np(val, np.float64)
+    rf = None if row_factors is None else _np(row_factors, np.float64)
+    if rf is not None and rf.size != n_angles * n_bins:
+        raise ValueError("row_factors needs one entry per ray")
+    h = C.c_void_p()
+    _call("appga_load_system_matrix_factored", ctx, C.byref(geom), len(cl), _ptr(rp), _ptr(cl), _ptr(vl),
+          DTYPES.get(storage, storage), _ptr(rf), float(psf_fwhm_px), C.byref(h))
+    _MAT_DIMS[h.value] = (n_angles * n_bins, n * n)
+    return h.value
+
+
+def appga_matrix_psf(mat) -> tuple:
+    """(FWHM in pixels, tap radius R) of a matrix's PSF; (0.0, -1) without one."""
+    fw, R = D(), I32()
+    _call("appga_matrix_psf", mat, C.byref(fw), C.byref(R))
+    return fw.value, R.value
 
 
 def appga_free_system_matrix(ctx, mat) -> None:

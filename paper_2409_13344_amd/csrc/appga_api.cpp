@@ -486,18 +486,65 @@ extern "C" appga_status appga_validate_params(const appga_params *p) {
     return validate_params(p);
 }
 
-extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geometry *geom,
-                                                 int64_t nnz, const int64_t *row_ptr,
-                                                 const int32_t *col_idx, const double *values,
-                                                 appga_dtype storage, appga_matrix **out) {
-    clear_error();
+// Gaussian PSF taps (Section 4.1): FWHM in pixels, sigma = FWHM / (2 sqrt(2 ln 2)),
+// offsets -R..R with R = ceil(3 sigma), normalised to sum 1.
+static std::vector<double> psf_taps_host(double fwhm, int &R) {
+    const double sigma = fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    R = static_cast<int>(std::ceil(3.0 * sigma));
+    std::vector<double> w(2 * R + 1);
+    double sum = 0.0;
+    for (int t = -R; t <= R; ++t) sum += (w[t + R] = std::exp(-static_cast<double>(t) * t / (2.0 * sigma * sigma)));
+    for (double &v : w) v /= sum;
+    return w;
+}
+
+// One FP64 pass of H on the host along axis 0 (columns c) or 1 (rows r), zero outside.
+static void psf_pass_host(int n, const std::vector<double> &w, int axis, const std::vector<double> &in,
+                          std::vector<double> &out) {
+    const int R = (static_cast<int>(w.size()) - 1) / 2;
+    out.assign(static_cast<size_t>(n) * n, 0.0);
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k <= 2 * R; ++k) {
+                const int q = (axis == 0 ? c : r) + k - R;
+                if (q < 0 || q >= n) continue;
+                acc += w[k] * in[axis == 0 ? static_cast<size_t>(r) * n + q : static_cast<size_t>(q) * n + c];
+            }
+            out[static_cast<size_t>(r) * n + c] = acc;
+        }
+}
+
+static appga_status load_impl(appga_ctx *ctx, const appga_geometry *geom, int64_t nnz, const int64_t *row_ptr,
+                              const int32_t *col_idx, const double *values_in, appga_dtype storage,
+                              const double *row_factors, double psf_fwhm, appga_matrix **out) {
     if (!ctx || !geom || !out) return fail(APPGA_E_INVALID_ARG, "NULL ctx, geometry or output");
     if (storage != APPGA_F32 && storage != APPGA_BF16 && storage != APPGA_F16 &&
         storage != APPGA_FP8_E4M3_ROWSCALE)
         return fail(APPGA_E_INVALID_ARG, "unknown storage type %d", static_cast<int>(storage));
-    ST_TRY(check_matrix(geom, nnz, row_ptr, col_idx, values));
+    ST_TRY(check_matrix(geom, nnz, row_ptr, col_idx, values_in));
     const int64_t m = static_cast<int64_t>(geom->n_angles) * geom->n_bins;
     const int64_t d = static_cast<int64_t>(geom->n) * geom->n;
+    if (!std::isfinite(psf_fwhm) || psf_fwhm < 0.0) return fail(APPGA_E_DOMAIN, "psf_fwhm_px must be >= 0");
+    int psf_R = -1;
+    std::vector<double> taps;
+    if (psf_fwhm > 0.0) {
+        if (psf_fwhm > 24.0) return fail(APPGA_E_DOMAIN, "psf_fwhm_px must be <= 24 pixels");
+        taps = psf_taps_host(psf_fwhm, psf_R);
+        if (2 * psf_R + 1 > kPsfMaxTaps) return fail(APPGA_E_DOMAIN, "PSF too wide");
+    }
+    // A = diag(row factors) G: the factors are folded into the stored values
+    std::vector<double> scaled;
+    const double *values = values_in;
+    if (row_factors) {
+        for (int64_t i = 0; i < m; ++i)
+            if (!std::isfinite(row_factors[i]) || row_factors[i] < 0.0)
+                return fail(APPGA_E_DOMAIN, "row factor %lld is negative or not finite", (long long)i);
+        scaled.resize(nnz);
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) scaled[k] = values_in[k] * row_factors[i];
+        values = scaled.data();
+    }
     HIP_TRY(hipSetDevice(ctx->device));
     const int vtype = static_cast<int>(storage);
 
@@ -511,6 +558,9 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
     mat->deq.assign(nnz, 0.0);
     mat->user_row_ptr.assign(row_ptr, row_ptr + m + 1);
     mat->user_col.assign(col_idx, col_idx + nnz);
+    mat->has_row_factors = row_factors != nullptr;
+    mat->psf_fwhm = psf_fwhm;
+    mat->psf_R = psf_R;
 
     // stored transpose: rows = pixels, entries ordered by detector row
     std::vector<int64_t> trp(d + 1, 0);
@@ -573,10 +623,21 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
                             env_int("APPGA_FWD_PART_WINDOWS", 0)))
             st = gather_tiles_to_device(hf, mat->ft);
     }
+    if (st == APPGA_OK && psf_R >= 0) {
+        std::vector<float> tf(taps.begin(), taps.end());
+        int64_t dummy = 0;
+        st = upload(tf, reinterpret_cast<void **>(&mat->psf_taps), dummy);
+    }
     if (st == APPGA_OK) {
-        // Lambda = A^T 1 of the stored (dequantised) values, zeros -> 1 (eq. EM)
+        // Lambda = A^T 1 of the stored (dequantised) values, zeros -> 1 (eq. EM);
+        // with a PSF, A^T 1 = H (G^T n) (H is symmetric)
         std::vector<double> lam(d, 0.0);
         for (int64_t k = 0; k < nnz; ++k) lam[col_idx[k]] += mat->deq[k];
+        if (psf_R >= 0) {
+            std::vector<double> t1;
+            psf_pass_host(geom->n, taps, 0, lam, t1);
+            psf_pass_host(geom->n, taps, 1, t1, lam);
+        }
         std::vector<float> lamf(d);
         for (int64_t j = 0; j < d; ++j) lamf[j] = lam[j] > 0.0 ? static_cast<float>(lam[j]) : 1.0f;
         int64_t dummy = 0;
@@ -588,6 +649,7 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
         free_gather_tiles(mat->bt);
         free_gather_tiles(mat->ft);
         hipFree(mat->lam);
+        hipFree(mat->psf_taps);
         delete mat;
         return st;
     }
@@ -611,6 +673,7 @@ extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geo
             free_gather_tiles(mat->bt);
             free_gather_tiles(mat->ft);
             hipFree(mat->lam);
+            hipFree(mat->psf_taps);
             delete mat;
             return ts;
         }
@@ -631,7 +694,32 @@ extern "C" appga_status appga_free_system_matrix(appga_ctx *ctx, appga_matrix *m
     free_gather_tiles(mat->bt);
     free_gather_tiles(mat->ft);
     hipFree(mat->lam);
+    hipFree(mat->psf_taps);
     delete mat;
+    return APPGA_OK;
+}
+
+extern "C" appga_status appga_load_system_matrix(appga_ctx *ctx, const appga_geometry *geom, int64_t nnz,
+                                                 const int64_t *row_ptr, const int32_t *col_idx,
+                                                 const double *values, appga_dtype storage, appga_matrix **out) {
+    clear_error();
+    return load_impl(ctx, geom, nnz, row_ptr, col_idx, values, storage, nullptr, 0.0, out);
+}
+
+extern "C" appga_status appga_load_system_matrix_factored(appga_ctx *ctx, const appga_geometry *geom,
+                                                          int64_t nnz, const int64_t *row_ptr,
+                                                          const int32_t *col_idx, const double *values,
+                                                          appga_dtype storage, const double *row_factors,
+                                                          double psf_fwhm_px, appga_matrix **out) {
+    clear_error();
+    return load_impl(ctx, geom, nnz, row_ptr, col_idx, values, storage, row_factors, psf_fwhm_px, out);
+}
+
+extern "C" appga_status appga_matrix_psf(const appga_matrix *mat, double *fwhm_px, int32_t *radius) {
+    clear_error();
+    if (!mat || !fwhm_px || !radius) return fail(APPGA_E_INVALID_ARG, "NULL argument");
+    *fwhm_px = mat->psf_R >= 0 ? mat->psf_fwhm : 0.0;
+    *radius = mat->psf_R;
     return APPGA_OK;
 }
 
@@ -851,6 +939,14 @@ double theta_of(const appga_params &p, int k) {
 
 namespace appga {
 
+hipError_t psf_blur(const appga_matrix *mat, const float *in, int n_parts, float *tmp, float *out, int B, int Bp,
+                    hipStream_t st) {
+    const int n = mat->geom.n;
+    hipError_t he = launch_psf_pass(in, n_parts, tmp, n, B, Bp, 0, mat->psf_taps, mat->psf_R, st);
+    if (he == hipSuccess) he = launch_psf_pass(tmp, 1, out, n, B, Bp, 1, mat->psf_taps, mat->psf_R, st);
+    return he;
+}
+
 static appga_status sess_alloc(appga_solve *s) {
     const int B = s->B;
     const int64_t m = s->mat->A.n_rows, d = s->mat->A.n_cols;
@@ -877,7 +973,11 @@ static appga_status sess_alloc(appga_solve *s) {
     const bool tiles = B > 1 && s->mat->bt.valid;
     // AFPPA takes A^T e as its own pass in every layout (split partial sums with tiles)
     s->gf_split = tiles ? s->mat->bt_split : 1;
-    const bool need_gf = tiles || s->afppa;
+    const bool psf = s->mat->psf_R >= 0;
+    const bool need_gf = tiles || s->afppa || psf;
+    const size_t o_xb = psf ? take(sizeof(float) * d * Bp) : 0;
+    const size_t o_tb = psf ? take(sizeof(float) * d * Bp) : 0;
+    const size_t o_gfb = psf ? take(sizeof(float) * d * Bp) : 0;
     const size_t o_gf = need_gf ? take(sizeof(float) * d * Bp * s->gf_split) : 0;
     const size_t o_w = s->afppa ? take(sizeof(float) * d * Bp) : 0;
     const size_t o_y = s->afppa ? take(sizeof(float) * 6 * d * Bp) : 0;
@@ -906,6 +1006,11 @@ static appga_status sess_alloc(appga_solve *s) {
     s->e = reinterpret_cast<float *>(base + o_e);
     s->pbuf = s->need_pbuf ? reinterpret_cast<float *>(base + o_pb) : nullptr;
     s->gf = need_gf ? reinterpret_cast<float *>(base + o_gf) : nullptr;
+    if (psf) {
+        s->xb = reinterpret_cast<float *>(base + o_xb);
+        s->tb = reinterpret_cast<float *>(base + o_tb);
+        s->gfb = reinterpret_cast<float *>(base + o_gfb);
+    }
     if (s->afppa) {
         s->w = reinterpret_cast<float *>(base + o_w);
         s->ydual = reinterpret_cast<float *>(base + o_y);
@@ -963,6 +1068,10 @@ appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> 
     fa.B = B;
     fa.Bp = s->Bp;
     fa.x = x;
+    if (mat->psf_R >= 0) {   // A x = G (H x)
+        HIP_TRY(psf_blur(mat, x, 1, s->tb, s->xb, B, s->Bp, s->st));
+        fa.x = s->xb;
+    }
     fa.g = s->g;
     fa.gamma = s->gamma;
     fa.gamma_lane = s->gamma_lane;
@@ -1137,6 +1246,12 @@ static appga_status afppa_step(appga_solve *s, int n_iters) {
         fa.B = B;
         fa.Bp = Bp;
         fa.x = s->ft[s->cur];
+        if (mat->psf_R >= 0) {   // the forward takes H f~
+            HIP_TRY(timed_launch(s->ctx, "psf_fwd", s->st, [&] {
+                return psf_blur(mat, s->ft[s->cur], 1, s->tb, s->xb, B, Bp, s->st);
+            }));
+            fa.x = s->xb;
+        }
         fa.g = s->g;
         fa.gamma = s->gamma;
         fa.gamma_lane = s->gamma_lane;
@@ -1186,6 +1301,13 @@ static appga_status afppa_step(appga_solve *s, int n_iters) {
         aa.Bp = Bp;
         aa.gf = s->gf;
         aa.gf_split = s->gf_split;
+        if (mat->psf_R >= 0) {   // grad F = H (A^T e)
+            HIP_TRY(timed_launch(s->ctx, "psf_back", s->st, [&] {
+                return psf_blur(mat, s->gf, s->gf_split, s->tb, s->gfb, B, Bp, s->st);
+            }));
+            aa.gf = s->gfb;
+            aa.gf_split = 1;
+        }
         aa.f = s->f;
         aa.ft = s->ft[s->cur];
         aa.ft_next = s->ft[s->cur ^ 1];
@@ -1239,6 +1361,12 @@ appga_status sess_step(appga_solve *s, int n_iters) {
         fa.B = B;
         fa.Bp = s->Bp;
         fa.x = s->ft[s->cur];
+        if (mat->psf_R >= 0) {   // the forward takes H f~
+            HIP_TRY(timed_launch(s->ctx, "psf_fwd", s->st, [&] {
+                return psf_blur(mat, s->ft[s->cur], 1, s->tb, s->xb, B, s->Bp, s->st);
+            }));
+            fa.x = s->xb;
+        }
         fa.g = s->g;
         fa.gamma = s->gamma;
         fa.gamma_lane = s->gamma_lane;
@@ -1279,7 +1407,28 @@ appga_status sess_step(appga_solve *s, int n_iters) {
         sa.re_part = (it == n_iters - 1) ? s->part : nullptr;
         sa.tiles_x = (mat->geom.n + 3) / 4;
         sa.xcd_remap = mat->xcd_remap;
-        if (s->gf) {
+        if (mat->psf_R >= 0) {
+            // grad F = H (A^T e): the back projection on its own (tiles, or the step
+            // kernel's gather), then the blur; the step takes the result
+            if (B > 1 && mat->bt.valid) {
+                HIP_TRY(timed_launch(s->ctx, "back_tiles", s->st, [&] {
+                    return launch_back_tiles(mat->bt, mat->AT.vtype, mat->geom.n, mat->A.n_rows, s->Bp,
+                                             mat->bt_remap, mat->bt_split, s->e, s->gf, s->st);
+                }));
+            } else {
+                StepArgs sb = sa;
+                sb.out_mode = SO_BACK;
+                sb.out = s->gf;
+                sb.re_part = nullptr;
+                HIP_TRY(timed_launch(s->ctx, B == 1 ? "back_single" : "back_batch", s->st,
+                                     [&] { return launch_step(mat->AT, sb, mat->group_back, s->st); }));
+            }
+            HIP_TRY(timed_launch(s->ctx, "psf_back", s->st, [&] {
+                return psf_blur(mat, s->gf, s->gf_split, s->tb, s->gfb, B, s->Bp, s->st);
+            }));
+            sa.gf_in = s->gfb;
+            sa.gf_split = 1;
+        } else if (s->gf) {
             HIP_TRY(timed_launch(s->ctx, "back_tiles", s->st, [&] {
                 return launch_back_tiles(mat->bt, mat->AT.vtype, mat->geom.n, mat->A.n_rows, s->Bp,
                                          mat->bt_remap, mat->bt_split, s->e, s->gf, s->st);
@@ -1620,11 +1769,17 @@ appga_status op_forward_impl(appga_ctx *ctx, const appga_matrix *mat, int B, con
     const int Bp = pad_lanes(B);
     OpBufs ob;
     const size_t ntp = B > 1 && mat->ft.valid ? fwd_tile_part_floats(mat->ft, Bp) : 0;
-    const size_t nf = static_cast<size_t>(d) * Bp + 3 * static_cast<size_t>(m) * Bp + ntp;
+    const bool psf = mat->psf_R >= 0;
+    const size_t nf = static_cast<size_t>(d) * Bp * (psf ? 3 : 1) + 3 * static_cast<size_t>(m) * Bp + ntp;
     HIP_TRY(hipMalloc(&ob.mem, sizeof(float) * nf));
     float *x = static_cast<float *>(ob.mem), *g = x + d * Bp, *gam = g + m * Bp, *y = gam + m * Bp;
     float *tp = ntp ? y + m * Bp : nullptr;
+    float *xb = psf ? y + m * Bp + ntp : nullptr, *tb = psf ? xb + d * Bp : nullptr;
     ST_TRY(to_internal(d_x, x, B, d, st));
+    if (psf) {   // A x = diag(n) G (H x)
+        HIP_TRY(timed_launch(ctx, "op_psf", st, [&] { return psf_blur(mat, x, 1, tb, xb, B, Bp, st); }));
+        x = xb;
+    }
     if (d_g) ST_TRY(to_internal(d_g, g, B, m, st));
     if (d_gamma) ST_TRY(to_internal(d_gamma, gam, B, m, st));
     FwdArgs fa{};
@@ -1664,6 +1819,9 @@ appga_status op_step_impl(appga_ctx *ctx, const appga_matrix *mat, int n, int B,
     const int64_t d = static_cast<int64_t>(n) * n;
     const int64_t m = mat ? mat->A.n_rows : 0;
     const int Bp = pad_lanes(B);
+    const bool psf = mat && mat->psf_R >= 0 && out_mode != SO_REG;
+    if (psf && out_mode != SO_BACK)
+        return fail(APPGA_E_INVALID_ARG, "appga_op_step does not model a PSF; use a session");
     OpBufs ob;
     const int split = mat ? mat->bt_split : 1;
     const size_t nfl = static_cast<size_t>(d) * Bp * (4 + split) + static_cast<size_t>(m) * Bp + Bp;
@@ -1733,6 +1891,10 @@ appga_status op_step_impl(appga_ctx *ctx, const appga_matrix *mat, int n, int B,
         sa.gf_split = split;
     }
     HIP_TRY(timed_launch(ctx, name, st, [&] { return launch_step(AT, sa, group, st); }));
+    if (psf) {   // A^T e = H (G^T diag(n) e): blur the back projection (f and ft_next serve as scratch)
+        HIP_TRY(timed_launch(ctx, "op_psf", st, [&] { return psf_blur(mat, out, 1, f, ftn, B, Bp, st); }));
+        out = ftn;
+    }
     if (out_mode == SO_STEP) {
         ST_TRY(from_internal(f, d_f, B, d, st));
         ST_TRY(from_internal(ftn, d_ft_next, B, d, st));

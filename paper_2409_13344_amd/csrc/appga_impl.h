@@ -46,6 +46,12 @@ struct appga_matrix {
     int fwd_wgs = 2048;                // batched forward: workgroups of the row-strided grid
     mutable std::atomic<int> inflight{0};
     uint64_t serial = 0;               // unique per load (servers key their pools by it)
+    // factored model (Section 4.1 physics): A = diag(row factors) G H with H a
+    // Gaussian PSF of 2 psf_R + 1 taps per axis (psf_R < 0: no PSF)
+    double psf_fwhm = 0.0;
+    int psf_R = -1;
+    float *psf_taps = nullptr;         // device, 2 psf_R + 1 floats
+    bool has_row_factors = false;
 };
 
 struct appga_solve {
@@ -81,6 +87,8 @@ struct appga_solve {
     // per-solve accumulators of max P (kAfppaPmSlots each, FP32 bits)
     bool afppa = false;
     float *w = nullptr, *ydual = nullptr, *ybar = nullptr;
+    // PSF sessions: H f~ (the forward's input), the blur's intermediate pass, and H A^T e
+    float *xb = nullptr, *tb = nullptr, *gfb = nullptr;
     unsigned *pm = nullptr;
     int gf_split = 1;
     int re_blocks = 0;   // workgroups that wrote the RE partial sums of the last step
@@ -128,5 +136,8 @@ inline bool forward_uses_tiles(const appga_matrix *mat, const appga::FwdArgs &fa
     return mat->ft.valid && fa.Bp >= 64;
 }
 void sess_free(appga_solve *s);
+// out = H in for a matrix with a PSF (in: n_parts partial sums; tmp: d * Bp floats).
+hipError_t psf_blur(const appga_matrix *mat, const float *in, int n_parts, float *tmp, float *out, int B,
+                    int Bp, hipStream_t st);
 
 }  // namespace appga

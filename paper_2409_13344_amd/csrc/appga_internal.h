@@ -219,6 +219,14 @@ struct AfppaArgs {
     double *re_part;           // primal: [blocks][Bp][2] sum (f^{k+1} - f^k)^2, sum (f^{k+1})^2 (or null)
 };
 
+// Space-invariant Gaussian PSF H (Section 4.1): one separable pass along the
+// image columns (axis 0: out(r, c) = sum_t w_t in(r, c + t - R)) or rows (axis 1),
+// zero outside the image.  `in` holds n_parts partial sums [n_parts][d][Bp]
+// added in order before the blur (n_parts = 1 for a plain image).  Layout of Bp.
+constexpr int kPsfMaxTaps = 65;
+hipError_t launch_psf_pass(const float *in, int n_parts, float *out, int n, int B, int Bp, int axis,
+                           const float *taps, int R, hipStream_t st);
+
 constexpr int kAfppaPmSlots = 32;
 
 // Workgroups of the AFPPA kernels (RE partial sums per workgroup).

@@ -440,8 +440,12 @@ __global__ __launch_bounds__(16 * G) void k_step_single(StepArgs a) {
         float acc = 0.0f;
         if (rp < N && cp < N) {
             const int j = rp * N + cp;
-            const auto er = make_rsrc(a.e, 4u * static_cast<uint32_t>(a.m));
-            acc = gather_dot_group<IT, VT, G>(col, a.val, er, a.row_ptr[j], a.row_ptr[j + 1], gl);
+            if (a.gf_in) {   // A^T e given (one partial sum): the group's first lane carries it
+                acc = gl == 0 ? a.gf_in[j] : 0.0f;
+            } else {
+                const auto er = make_rsrc(a.e, 4u * static_cast<uint32_t>(a.m));
+                acc = gather_dot_group<IT, VT, G>(col, a.val, er, a.row_ptr[j], a.row_ptr[j + 1], gl);
+            }
         }
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -1459,6 +1463,49 @@ hipError_t launch_step(const DevCsr &AT, const StepArgs &args, int group, hipStr
     return by_type(AT.idx16, AT.vtype, [&](auto it, auto vt) {
         return step_dispatch<decltype(it), decltype(vt)::value>(args, group, st);
     });
+}
+
+// One pass of the separable PSF blur.  Thread t is element t of the output in
+// the layout of Bp (lane layout: pixel (t / 64) % d of chunk t / (64 d)); the
+// 2R + 1 inputs along the pass's axis are read at indices clamped into the
+// image and weighted 0 outside it, so the loads carry no branches.
+template <bool LANES>
+__global__ __launch_bounds__(256) void k_psf_pass(const float *in, int n_parts, float *out, int n, int Bp,
+                                                  int axis, const float *taps, int R) {
+    const int d = n * n;
+    const size_t total = static_cast<size_t>(d) * Bp;
+    const size_t t = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (t >= total) return;
+    const int j = LANES ? static_cast<int>((t >> 6) % d) : static_cast<int>(t);
+    const size_t base = LANES ? (t / (static_cast<size_t>(d) * 64)) * static_cast<size_t>(d) * 64 + (t & 63) : 0;
+    const int r = j / n, c = j - r * n;
+    const int pos = axis == 0 ? c : r;
+    const size_t stride = static_cast<size_t>(d) * Bp;
+    float acc = 0.0f;
+    for (int k = 0; k <= 2 * R; ++k) {
+        const int q = pos + k - R;
+        const int qc = min(max(q, 0), n - 1);
+        const int jj = axis == 0 ? r * n + qc : qc * n + c;
+        const size_t o = LANES ? base + static_cast<size_t>(jj) * 64 : static_cast<size_t>(jj);
+        float v = in[o];
+        for (int p = 1; p < n_parts; ++p) v += in[p * stride + o];
+        acc += (q == qc ? taps[k] : 0.0f) * v;
+    }
+    out[t] = acc;
+}
+
+hipError_t launch_psf_pass(const float *in, int n_parts, float *out, int n, int B, int Bp, int axis,
+                           const float *taps, int R, hipStream_t st) {
+    (void)B;
+    if (R < 0 || 2 * R + 1 > kPsfMaxTaps || n_parts < 1 || (Bp != 1 && Bp % 64 != 0)) return hipErrorInvalidValue;
+    const size_t total = static_cast<size_t>(n) * n * Bp;
+    if (Bp == 1)
+        hipLaunchKernelGGL(k_psf_pass<false>, dim3(blocks_for(total)), dim3(256), 0, st, in, n_parts, out, n, Bp,
+                           axis, taps, R);
+    else
+        hipLaunchKernelGGL(k_psf_pass<true>, dim3(blocks_for(total)), dim3(256), 0, st, in, n_parts, out, n, Bp,
+                           axis, taps, R);
+    return hipGetLastError();
 }
 
 int afppa_blocks(int n, int Bp) {

@@ -617,6 +617,8 @@ extern "C" appga_status appga_submit(appga_server *srv, const appga_matrix *mat,
     clear_error();
     if (!srv || !mat || !g || !params || !ticket) return fail(APPGA_E_INVALID_ARG, "NULL argument");
     if (mat->ctx != srv->ctx) return fail(APPGA_E_INVALID_ARG, "matrix belongs to another context");
+    if (mat && mat->psf_R >= 0)
+        return fail(APPGA_E_INVALID_ARG, "serving does not model a PSF; use a session for this matrix");
     appga_status st = validate_params(params);
     if (st != APPGA_OK) return st;
     if (params->precond != APPGA_PRECOND_EM)
