@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--afppa-steps", type=int, default=200,
                     help="timed AFPPA-GN steps on the same workload (0 = skip the leg)")
     ap.add_argument("--afppa-cpu-iters", type=int, default=100)
+    ap.add_argument("--factored-steps", type=int, default=100,
+                    help="timed APPGA steps with the factored model (PSF, attenuation, scatter/randoms)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2000)
     ap.add_argument("--profile", action="store_true",
@@ -158,6 +160,66 @@ def afppa_leg(ap, torch, ctx, mat, pr, g_t, stream, args, s_val, s_idx):
     return dict(value=round(B * args.afppa_steps / dt, 1), unit="solve-iterations/s",
                 ms_per_step=round(1e3 * dt / args.afppa_steps, 4), steps=args.afppa_steps,
                 method="AFPPA-GN, omega = 1/2, beta = 1, EM preconditioner, lambda1 = lambda2 = 0.02",
+                kernels=kernels, objective_lane0=stats[0]["objective"])
+
+
+def factored_leg(ap, torch, ctx, args, stream):
+    """APPGA on Section 4.1's physics: 64 sinograms of the 128^2 geometry (the paper's 300 mm
+    field of view at half its resolution) with a Gaussian PSF of 6.59 mm (2.81 pixels), water
+    attenuation and 25% scatter / 25% randoms as a per-bin background; A = diag(n) G H."""
+    from paper_2409_13344_amd import synth
+    geom = synth.Geometry(128, 200, 168)
+    log("building the factored-model workload")
+    pp = synth.make_physics_problem(geom, list(range(4000, 4064)), tc=1e6, fov_mm=300.0,
+                                    G=synth.cached_matrix(geom))
+    B, d, m = len(pp.seeds), geom.d, geom.m
+    G = pp.G
+    mat = ap.appga_load_system_matrix_factored(ctx, geom.n, geom.n_angles, geom.n_bins, G.row_ptr, G.col, G.val,
+                                               args.storage, row_factors=pp.att, psf_fwhm_px=pp.fwhm_px)
+    psf_R = ap.appga_matrix_psf(mat)[1]
+    try:
+        dev = torch.device("cuda:0")
+        g_t = torch.as_tensor(pp.g).to(dev)
+        gam_t = torch.as_tensor(pp.gamma).to(dev)
+        params = [ap.make_params(lam=0.02, eps=1e-3, omega=0.5, iterations=300) for _ in range(B)]
+        sess = ap.appga_solve_begin(ctx, mat, g_t, gam_t, params, None, stream)
+        for _ in range(args.warmup):
+            ap.appga_solve_step(sess, 1)
+        torch.cuda.synchronize()
+        log("timing %d factored-model steps" % args.factored_steps)
+        t0 = time.perf_counter()
+        for _ in range(args.factored_steps):
+            ap.appga_solve_step(sess, 1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ap.appga_set_kernel_timing(ctx, True)
+        for _ in range(max(10, min(args.factored_steps, 100))):
+            ap.appga_solve_step(sess, 1)
+        torch.cuda.synchronize()
+        times = ap.appga_kernel_times(ctx)
+        ap.appga_set_kernel_timing(ctx, False)
+        out_t = torch.empty((B, d), dtype=torch.float32, device=dev)
+        stats = ap.appga_solve_end(sess, out_t, B)
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    kernels = {}
+    split = 2
+    for name in ("psf_fwd", "fwd_tiles", "back_tiles", "psf_back", "step_batch"):
+        t = times.get(name)
+        if not t or t["count"] == 0:
+            continue
+        avg_ms = t["total_ms"] / t["count"]
+        k = dict(avg_us=round(1e3 * avg_ms, 2))
+        if name.startswith("psf"):
+            # the blur reads its input (psf_back: the two partial back projections) and writes
+            # H of it, d x B floats each
+            nbytes = 4 * B * d * ((split if name == "psf_back" else 1) + 1)
+            k.update(bytes=nbytes, gbs=round(nbytes / (avg_ms * 1e-3) / 1e9, 1))
+        kernels[name] = k
+    return dict(value=round(B * args.factored_steps / dt, 1), unit="solve-iterations/s",
+                ms_per_step=round(1e3 * dt / args.factored_steps, 4), steps=args.factored_steps,
+                model="A = diag(att) G H: PSF FWHM %.2f px (R = %d), water attenuation, per-bin "
+                      "scatter + randoms background" % (pp.fwhm_px, psf_R),
                 kernels=kernels, objective_lane0=stats[0]["objective"])
 
 
@@ -388,6 +450,11 @@ def main():
             log("timing the FP64 AFPPA oracle on the host cores")
             afppa["cpu_oracle"] = cpu_baseline_afppa(pr, args.afppa_cpu_iters)
 
+    # ------------------------------------- factored model (Section 4.1) ---
+    factored = None
+    if args.factored_steps > 0:
+        factored = factored_leg(ap, torch, ctx, args, stream)
+
     # ----------------------------------------------------- plain (B = 1) ---
     plain = None
     if not args.profile:
@@ -476,6 +543,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "afppa": afppa,
+        "factored": factored,
         "serving": serving,
         "projector_single_256": projector,
         "matrix_bytes": info,

@@ -1465,46 +1465,60 @@ hipError_t launch_step(const DevCsr &AT, const StepArgs &args, int group, hipStr
     });
 }
 
-// One pass of the separable PSF blur.  Thread t is element t of the output in
-// the layout of Bp (lane layout: pixel (t / 64) % d of chunk t / (64 d)); the
-// 2R + 1 inputs along the pass's axis are read at indices clamped into the
-// image and weighted 0 outside it, so the loads carry no branches.
-template <bool LANES>
+// One pass of the separable PSF blur.  Grid: blockIdx.y = chunk of 64 solves
+// (Bp == 1: one chunk of one solve); within a chunk, thread u is pixel u / 64,
+// lane u % 64 (Bp == 1: pixel u).  The 2R + 1 inputs along the pass's axis are
+// read at indices clamped into the image and weighted 0 outside it, so the
+// loads carry no branches.  SPLIT: partial sums of the input added first
+// (1 or 2; 0 = n_parts at run time).
+template <bool LANES, int SPLIT>
 __global__ __launch_bounds__(256) void k_psf_pass(const float *in, int n_parts, float *out, int n, int Bp,
                                                   int axis, const float *taps, int R) {
     const int d = n * n;
-    const size_t total = static_cast<size_t>(d) * Bp;
-    const size_t t = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (t >= total) return;
-    const int j = LANES ? static_cast<int>((t >> 6) % d) : static_cast<int>(t);
-    const size_t base = LANES ? (t / (static_cast<size_t>(d) * 64)) * static_cast<size_t>(d) * 64 + (t & 63) : 0;
+    const int u = blockIdx.x * 256 + threadIdx.x;
+    if (u >= (LANES ? d * 64 : d)) return;
+    const int j = LANES ? (u >> 6) : u;
+    const size_t base = LANES ? static_cast<size_t>(blockIdx.y) * d * 64 + (u & 63) : 0;
     const int r = j / n, c = j - r * n;
     const int pos = axis == 0 ? c : r;
     const size_t stride = static_cast<size_t>(d) * Bp;
     float acc = 0.0f;
+#pragma unroll 9
     for (int k = 0; k <= 2 * R; ++k) {
         const int q = pos + k - R;
         const int qc = min(max(q, 0), n - 1);
         const int jj = axis == 0 ? r * n + qc : qc * n + c;
         const size_t o = LANES ? base + static_cast<size_t>(jj) * 64 : static_cast<size_t>(jj);
         float v = in[o];
-        for (int p = 1; p < n_parts; ++p) v += in[p * stride + o];
+        if (SPLIT == 2) v += in[stride + o];
+        if (SPLIT == 0)
+            for (int p = 1; p < n_parts; ++p) v += in[p * stride + o];
         acc += (q == qc ? taps[k] : 0.0f) * v;
     }
-    out[t] = acc;
+    out[base + (LANES ? static_cast<size_t>(j) * 64 : static_cast<size_t>(j))] = acc;
 }
 
 hipError_t launch_psf_pass(const float *in, int n_parts, float *out, int n, int B, int Bp, int axis,
                            const float *taps, int R, hipStream_t st) {
     (void)B;
     if (R < 0 || 2 * R + 1 > kPsfMaxTaps || n_parts < 1 || (Bp != 1 && Bp % 64 != 0)) return hipErrorInvalidValue;
-    const size_t total = static_cast<size_t>(n) * n * Bp;
-    if (Bp == 1)
-        hipLaunchKernelGGL(k_psf_pass<false>, dim3(blocks_for(total)), dim3(256), 0, st, in, n_parts, out, n, Bp,
-                           axis, taps, R);
-    else
-        hipLaunchKernelGGL(k_psf_pass<true>, dim3(blocks_for(total)), dim3(256), 0, st, in, n_parts, out, n, Bp,
-                           axis, taps, R);
+    const int d = n * n;
+    const dim3 block(256);
+    if (Bp == 1) {
+        const dim3 grid((d + 255) / 256, 1);
+        if (n_parts == 1)
+            hipLaunchKernelGGL((k_psf_pass<false, 1>), grid, block, 0, st, in, n_parts, out, n, Bp, axis, taps, R);
+        else
+            hipLaunchKernelGGL((k_psf_pass<false, 0>), grid, block, 0, st, in, n_parts, out, n, Bp, axis, taps, R);
+    } else {
+        const dim3 grid((d * 64 + 255) / 256, Bp / 64);
+        if (n_parts == 1)
+            hipLaunchKernelGGL((k_psf_pass<true, 1>), grid, block, 0, st, in, n_parts, out, n, Bp, axis, taps, R);
+        else if (n_parts == 2)
+            hipLaunchKernelGGL((k_psf_pass<true, 2>), grid, block, 0, st, in, n_parts, out, n, Bp, axis, taps, R);
+        else
+            hipLaunchKernelGGL((k_psf_pass<true, 0>), grid, block, 0, st, in, n_parts, out, n, Bp, axis, taps, R);
+    }
     return hipGetLastError();
 }
 
