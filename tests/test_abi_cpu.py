@@ -101,3 +101,39 @@ def test_matrix_validation():
     v = A.val.copy()
     v[3] = np.nan
     expect(-6, val=v)                                      # non-finite
+
+
+def test_binding_checks_device_buffer_sizes():
+    """The device calls cannot see a buffer's length: the binding checks every tensor
+    against the matrix's (m, d) and the session's (B, m, d) before a call reaches the
+    library (here the calls never get that far)."""
+    torch = pytest.importorskip("torch")
+    fake_mat = 0x1234
+    ap._MAT_DIMS[fake_mat] = (10, 4)
+    try:
+        g_ok = torch.zeros((2, 10), dtype=torch.float32)
+        with pytest.raises(ValueError, match="g holds 10 elements, needs 20"):
+            ap.appga_solve_begin(0, fake_mat, torch.zeros((1, 10)), None, [ap.appga_params_default()] * 2)
+        with pytest.raises(ValueError, match="gamma holds"):
+            ap.appga_afppa_begin(0, fake_mat, g_ok, torch.zeros((1, 10)), [ap.appga_params_default()] * 2)
+        with pytest.raises(ValueError, match="f_init"):
+            ap.appga_reconstruct_batch_device(0, fake_mat, g_ok, None, [ap.appga_params_default()] * 2,
+                                              torch.zeros(7), torch.zeros(8))
+        with pytest.raises(ValueError, match="float32"):
+            ap.appga_afppa_batch_device(0, fake_mat, g_ok.double(), None, [ap.appga_params_default()] * 2,
+                                        None, torch.zeros(8))
+        with pytest.raises(ValueError, match="duals"):
+            ap.appga_afppa_batch_device(0, fake_mat, g_ok, None, [ap.appga_params_default()] * 2, None,
+                                        torch.zeros(8), torch.zeros(47))
+        with pytest.raises(ValueError, match="contiguous"):
+            ap.appga_reconstruct_batch_device(0, fake_mat, torch.zeros((10, 2)).t(), None,
+                                              [ap.appga_params_default()] * 2, None, torch.zeros(8))
+        with pytest.raises(ValueError, match="do not match the matrix"):
+            ap.appga_reconstruct_batch(0, fake_mat, 4, np.zeros((2, 10)), np.zeros((1, 10)),
+                                       [ap.appga_params_default()] * 2)
+        with pytest.raises(ValueError, match="do not match the matrix"):
+            ap.appga_afppa_batch(0, fake_mat, 5, np.zeros((2, 10)), None, [ap.appga_params_default()] * 2)
+        with pytest.raises(ValueError, match="unknown matrix"):
+            ap.appga_solve_begin(0, 0x999, g_ok, None, [ap.appga_params_default()] * 2)
+    finally:
+        ap._MAT_DIMS.pop(fake_mat, None)
