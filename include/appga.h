@@ -152,6 +152,17 @@ appga_status appga_load_system_matrix_factored(appga_ctx *ctx, const appga_geome
                                                const double *values, appga_dtype storage,
                                                const double *row_factors, double psf_fwhm_px,
                                                appga_matrix **out);
+/* Quarter-turn symmetry of a loaded matrix: with an even number of angles on
+ * the square grid, row (a + n_angles/2, b) is row (a, b) with pixel (r, c)
+ * moved to (c, N-1-r).  When every such pair agrees to 1e-9 of its largest
+ * entry (checked at load when the environment sets APPGA_SYMMETRY=1; FP32,
+ * BF16 or FP16 storage, d <= 65536), the single-solve (B = 1) kernels read
+ * only the first half of the rows and of the transpose and generate the rest
+ * by the pixel map, halving their matrix bytes and memory (not their time:
+ * they are bound by per-entry gathers of the image).  *folds = 2 then, else 1;
+ * *stored_bytes (may be NULL) = the bytes those kernels read per forward +
+ * back pair. */
+appga_status appga_matrix_symmetry(const appga_matrix *mat, int32_t *folds, int64_t *stored_bytes);
 /* The PSF of a loaded matrix: *fwhm_px (0 when none) and the tap radius *radius (-1 when none). */
 appga_status appga_matrix_psf(const appga_matrix *mat, double *fwhm_px, int32_t *radius);
 appga_status appga_free_system_matrix(appga_ctx *ctx, appga_matrix *mat);

@@ -78,6 +78,7 @@ _SIGS = {
     "appga_free_system_matrix": [P, P],
     "appga_load_system_matrix_factored": [P, C.POINTER(appga_geometry), I64, P, P, P, C.c_int, P, D, PP],
     "appga_matrix_psf": [P, C.POINTER(D), C.POINTER(I32)],
+    "appga_matrix_symmetry": [P, C.POINTER(I32), C.POINTER(I64)],
     "appga_matrix_info": [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I32)],
     "appga_matrix_dequantized": [P, P],
     "appga_reconstruct": [P, P, P, P, C.POINTER(appga_params), P, P, C.POINTER(appga_stats)],
@@ -259,6 +260,14 @@ def appga_load_system_matrix_factored(ctx, n, n_angles, n_bins, row_ptr, col, va
           DTYPES.get(storage, storage), _ptr(rf), float(psf_fwhm_px), C.byref(h))
     _MAT_DIMS[h.value] = (n_angles * n_bins, n * n)
     return h.value
+
+
+def appga_matrix_symmetry(mat) -> tuple:
+    """(folds, stored bytes of the single-solve operators): folds = 2 when the B = 1
+    kernels read a half-stored matrix (quarter-turn symmetry), else 1."""
+    f, b = I32(), I64()
+    _call("appga_matrix_symmetry", mat, C.byref(f), C.byref(b))
+    return f.value, b.value
 
 
 def appga_matrix_psf(mat) -> tuple:

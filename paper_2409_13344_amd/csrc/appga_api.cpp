@@ -595,6 +595,69 @@ static appga_status load_impl(appga_ctx *ctx, const appga_geometry *geom, int64_
         if (st == APPGA_OK) st = to_device(ha, m, d, nnz, vtype, mat->A);
         if (st == APPGA_OK) st = to_device(ht, d, m, nnz, vtype, mat->AT);
     }
+    // quarter-turn symmetry (B = 1, opt-in with APPGA_SYMMETRY=1): row (a + A/2, b) is
+    // row (a, b) with pixel j moved to rho(j), rho(r, c) = (c, N - 1 - r), when the
+    // angles are even in number and every such pair agrees to 1e-9 of the row's largest
+    // entry; then the B = 1 kernels read only the first half of the rows and of the
+    // transpose.  It halves their matrix bytes and memory; it does not make them faster
+    // (they are bound by the rate of per-entry gathers of x, not by matrix bytes), hence
+    // off by default
+    if (st == APPGA_OK && env_int("APPGA_SYMMETRY", 0) && geom->n_angles % 2 == 0 && vtype != VT_FP8 &&
+        mat->A.idx16 && mat->AT.idx16) {
+        const int64_t half = m / 2;
+        const int N = geom->n;
+        bool ok = true;
+        std::vector<std::pair<int32_t, double>> ra, rb;
+        for (int64_t i = 0; i < half && ok; ++i) {
+            ra.clear();
+            rb.clear();
+            double big = 0.0;
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+                const int32_t r = col_idx[k] / N, c = col_idx[k] % N;
+                ra.emplace_back(c * N + (N - 1 - r), values[k]);
+                big = std::max(big, std::fabs(values[k]));
+            }
+            for (int64_t k = row_ptr[i + half]; k < row_ptr[i + half + 1]; ++k) {
+                rb.emplace_back(col_idx[k], values[k]);
+                big = std::max(big, std::fabs(values[k]));
+            }
+            std::sort(ra.begin(), ra.end());
+            std::sort(rb.begin(), rb.end());
+            const double tol = 1e-9 * std::max(big, 1e-300);
+            size_t p = 0, q = 0;
+            while (ok && (p < ra.size() || q < rb.size())) {
+                if (q == rb.size() || (p < ra.size() && ra[p].first < rb[q].first)) {
+                    ok = std::fabs(ra[p++].second) <= tol;
+                } else if (p == ra.size() || rb[q].first < ra[p].first) {
+                    ok = std::fabs(rb[q++].second) <= tol;
+                } else {
+                    ok = std::fabs(ra[p++].second - rb[q++].second) <= tol;
+                }
+            }
+        }
+        if (ok && half > 0) {
+            // the transpose of the first half: rows = pixels, entries = base rays in order
+            std::vector<int64_t> hrp(d + 1, 0);
+            for (int64_t k = 0; k < row_ptr[half]; ++k) hrp[col_idx[k] + 1] += 1;
+            for (int64_t j = 0; j < d; ++j) hrp[j + 1] += hrp[j];
+            const int64_t hnnz = row_ptr[half];
+            std::vector<int32_t> hcol(hnnz);
+            std::vector<double> hval(hnnz);
+            std::vector<int64_t> pos(hrp.begin(), hrp.end() - 1);
+            for (int64_t i = 0; i < half; ++i)
+                for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+                    const int64_t p2 = pos[col_idx[k]]++;
+                    hcol[p2] = static_cast<int32_t>(i);
+                    hval[p2] = values[k];
+                }
+            HostPacked hh, hth;
+            st = pack_rows(half, d, row_ptr, col_idx, values, vtype, hh, nullptr);
+            if (st == APPGA_OK) st = pack_rows(d, half, hrp.data(), hcol.data(), hval.data(), vtype, hth, nullptr);
+            if (st == APPGA_OK) st = to_device(hh, half, d, hnnz, vtype, mat->A_half);
+            if (st == APPGA_OK) st = to_device(hth, d, half, hnnz, vtype, mat->AT_half);
+            if (st == APPGA_OK) mat->sym = (mat->A_half.idx16 && mat->AT_half.idx16) ? 1 : 0;
+        }
+    }
     // tile forms for batches (B > 1); without them the row kernels serve
     if (st == APPGA_OK && env_int("APPGA_BACK_TILES", 1)) {
         // value of each transpose entry as the stored transpose decodes it
@@ -646,6 +709,8 @@ static appga_status load_impl(appga_ctx *ctx, const appga_geometry *geom, int64_
     if (st != APPGA_OK) {
         free_csr(mat->A);
         free_csr(mat->AT);
+        free_csr(mat->A_half);
+        free_csr(mat->AT_half);
         free_gather_tiles(mat->bt);
         free_gather_tiles(mat->ft);
         hipFree(mat->lam);
@@ -670,6 +735,8 @@ static appga_status load_impl(appga_ctx *ctx, const appga_geometry *geom, int64_
         if (ts != APPGA_OK) {
             free_csr(mat->A);
             free_csr(mat->AT);
+            free_csr(mat->A_half);
+            free_csr(mat->AT_half);
             free_gather_tiles(mat->bt);
             free_gather_tiles(mat->ft);
             hipFree(mat->lam);
@@ -691,6 +758,8 @@ extern "C" appga_status appga_free_system_matrix(appga_ctx *ctx, appga_matrix *m
     hipStreamSynchronize(ctx->stream);
     free_csr(mat->A);
     free_csr(mat->AT);
+    free_csr(mat->A_half);
+    free_csr(mat->AT_half);
     free_gather_tiles(mat->bt);
     free_gather_tiles(mat->ft);
     hipFree(mat->lam);
@@ -713,6 +782,14 @@ extern "C" appga_status appga_load_system_matrix_factored(appga_ctx *ctx, const 
                                                           double psf_fwhm_px, appga_matrix **out) {
     clear_error();
     return load_impl(ctx, geom, nnz, row_ptr, col_idx, values, storage, row_factors, psf_fwhm_px, out);
+}
+
+extern "C" appga_status appga_matrix_symmetry(const appga_matrix *mat, int32_t *folds, int64_t *stored_bytes) {
+    clear_error();
+    if (!mat || !folds) return fail(APPGA_E_INVALID_ARG, "NULL argument");
+    *folds = mat->sym ? 2 : 1;
+    if (stored_bytes) *stored_bytes = mat->sym ? mat->A_half.bytes + mat->AT_half.bytes : mat->A.bytes + mat->AT.bytes;
+    return APPGA_OK;
 }
 
 extern "C" appga_status appga_matrix_psf(const appga_matrix *mat, double *fwhm_px, int32_t *radius) {
@@ -1044,9 +1121,38 @@ static appga_status sess_theta(appga_solve *s, int k0) {
 }
 
 // FP64 objective Phi(x) per solve (Section 2.1) into host vector out.
+hipError_t launch_forward_single(const appga_matrix *mat, const FwdArgs &fa, int group, hipStream_t st) {
+    if (fa.B == 1 && mat->sym) {
+        FwdArgs h = fa;
+        h.row_ptr = mat->A_half.row_ptr;
+        h.col = mat->A_half.col;
+        h.col32 = mat->A_half.col32;
+        h.nnz_padded = mat->A_half.nnz_padded;
+        h.val = mat->A_half.val;
+        h.sym_half = mat->A.n_rows / 2;
+        h.img_n = mat->geom.n;
+        return launch_forward(mat->A_half, h, group, st);
+    }
+    return launch_forward(mat->A, fa, group, st);
+}
+
 hipError_t launch_forward_mat(const appga_matrix *mat, const FwdArgs &fa, hipStream_t st) {
     if (forward_uses_tiles(mat, fa)) return launch_fwd_tiles(mat->ft, mat->A.vtype, fa, st);
-    return launch_forward(mat->A, fa, mat->group_fwd, st);
+    return launch_forward_single(mat, fa, mat->group_fwd, st);
+}
+
+hipError_t launch_step_mat(const appga_matrix *mat, const StepArgs &sa, int group, hipStream_t st) {
+    if (sa.B == 1 && mat->sym) {
+        StepArgs h = sa;
+        h.row_ptr = mat->AT_half.row_ptr;
+        h.col = mat->AT_half.col;
+        h.col32 = mat->AT_half.col32;
+        h.nnz_padded = mat->AT_half.nnz_padded;
+        h.val = mat->AT_half.val;
+        h.sym_half = mat->A.n_rows / 2;
+        return launch_step(mat->AT_half, h, group, st);
+    }
+    return launch_step(mat->AT, sa, group, st);
 }
 
 appga_status sess_objective(appga_solve *s, const float *x, std::vector<double> &out,
@@ -1293,7 +1399,7 @@ static appga_status afppa_step(appga_solve *s, int n_iters) {
             sa.tiles_x = (mat->geom.n + 3) / 4;
             sa.xcd_remap = mat->xcd_remap;
             HIP_TRY(timed_launch(s->ctx, B == 1 ? "back_single" : "back_batch", s->st,
-                                 [&] { return launch_step(mat->AT, sa, mat->group_back, s->st); }));
+                                 [&] { return launch_step_mat(mat, sa, mat->group_back, s->st); }));
         }
         AfppaArgs aa{};
         aa.n = mat->geom.n;
@@ -1421,7 +1527,7 @@ appga_status sess_step(appga_solve *s, int n_iters) {
                 sb.out = s->gf;
                 sb.re_part = nullptr;
                 HIP_TRY(timed_launch(s->ctx, B == 1 ? "back_single" : "back_batch", s->st,
-                                     [&] { return launch_step(mat->AT, sb, mat->group_back, s->st); }));
+                                     [&] { return launch_step_mat(mat, sb, mat->group_back, s->st); }));
             }
             HIP_TRY(timed_launch(s->ctx, "psf_back", s->st, [&] {
                 return psf_blur(mat, s->gf, s->gf_split, s->tb, s->gfb, B, s->Bp, s->st);
@@ -1437,7 +1543,7 @@ appga_status sess_step(appga_solve *s, int n_iters) {
             sa.gf_split = mat->bt_split;
         }
         HIP_TRY(timed_launch(s->ctx, B == 1 ? "step_single" : "step_batch", s->st,
-                             [&] { return launch_step(mat->AT, sa, mat->group_back, s->st); }));
+                             [&] { return launch_step_mat(mat, sa, mat->group_back, s->st); }));
         s->cur ^= 1;
         s->k += 1;
         s->re_valid = (it == n_iters - 1);
@@ -1890,7 +1996,9 @@ appga_status op_step_impl(appga_ctx *ctx, const appga_matrix *mat, int n, int B,
         sa.gf_in = gf;
         sa.gf_split = split;
     }
-    HIP_TRY(timed_launch(ctx, name, st, [&] { return launch_step(AT, sa, group, st); }));
+    HIP_TRY(timed_launch(ctx, name, st, [&] {
+        return mat ? launch_step_mat(mat, sa, group, st) : launch_step(AT, sa, group, st);
+    }));
     if (psf) {   // A^T e = H (G^T diag(n) e): blur the back projection (f and ft_next serve as scratch)
         HIP_TRY(timed_launch(ctx, "op_psf", st, [&] { return psf_blur(mat, out, 1, f, ftn, B, Bp, st); }));
         out = ftn;

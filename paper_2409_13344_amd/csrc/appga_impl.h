@@ -34,6 +34,11 @@ struct appga_matrix {
     appga::DevCsr A, AT;
     appga::DevGatherTiles bt;          // B > 1 back projection over pixel tiles (bt.valid = 0: none)
     appga::DevGatherTiles ft;          // B > 1 forward projection over ray tiles (ft.valid = 0: none)
+    // B = 1 with quarter-turn symmetry: the first half of A's rows (angles below
+    // 90 degrees) and their transpose; the other half is the first turned by 90
+    // degrees (sym = 0: not used)
+    int sym = 0;
+    appga::DevCsr A_half, AT_half;
     float *lam = nullptr;              // Lambda (d), device
     std::vector<double> deq;           // dequantised values in the caller's CSR order
     std::vector<int64_t> user_row_ptr; // caller's CSR structure (for reports)
@@ -132,6 +137,12 @@ appga_status tune_matrix(appga_ctx *ctx, appga_matrix *mat, int flags, appga_tun
 // batch fills 64-lane chunks, else the row kernels.  *name (optional)
 // receives the kernel timing name.
 hipError_t launch_forward_mat(const appga_matrix *mat, const appga::FwdArgs &fa, hipStream_t st);
+// B = 1 forward row kernel with `group` lanes per row on the stored matrix (the
+// half-stored one with quarter-turn symmetry).
+hipError_t launch_forward_single(const appga_matrix *mat, const appga::FwdArgs &fa, int group, hipStream_t st);
+// The back-projection / step kernel on the matrix's stored transpose (the half-stored
+// one for B = 1 with quarter-turn symmetry); `group` lanes per pixel row for B = 1.
+hipError_t launch_step_mat(const appga_matrix *mat, const appga::StepArgs &sa, int group, hipStream_t st);
 inline bool forward_uses_tiles(const appga_matrix *mat, const appga::FwdArgs &fa) {
     return mat->ft.valid && fa.Bp >= 64;
 }

@@ -157,6 +157,11 @@ struct FwdArgs {
     int fwd_wgs;            // B > 1: workgroups of the row-strided grid (0 = default)
     unsigned long long *clamps;  // floored-bin counter (may be null)
     float *tile_part;       // forward tiles with split tiles: [chunks][n_pslots][64][64] scratch
+    // B = 1 with a half-stored matrix (quarter-turn symmetry): rows i >= sym_half
+    // are stored row i - sym_half with every column j mapped to rho(j),
+    // rho(r, c) = (c, N - 1 - r), N = img_n; 0 = the full matrix is stored
+    int sym_half;
+    int img_n;
 };
 
 struct StepArgs {
@@ -186,6 +191,10 @@ struct StepArgs {
     double *re_part;         // [blocks][B][2] sum (f^{k+1}-f^k)^2, sum (f^{k+1})^2 (or null)
     int tiles_x;             // tiles per image row
     int xcd_remap;           // 1: map workgroups to spatially compact tile blocks per XCD
+    // B = 1 with a half-stored transpose (quarter-turn symmetry): A^T e at pixel j
+    // is stored row j with e, plus stored row rho^{-1}(j) with e shifted by sym_half
+    // (rho^{-1}(r, c) = (N - 1 - c, r)); 0 = the full transpose is stored
+    int sym_half;
 };
 
 // One AFPPA iteration after the ratio forward projection and the back

@@ -208,7 +208,17 @@ template <typename IT, int VT, int G>
 __device__ __forceinline__ float gather_dot_group(const IT *__restrict__ col,
                                                   const void *__restrict__ val,
                                                   __amdgpu_buffer_rsrc_t xr, int k0, int k1,
-                                                  int gl) {
+                                                  int gl, int rot_n = 0) {
+    // rot_n > 0: gather x at rho(col), rho(r, c) = (c, N - 1 - r) for N = rot_n.
+    // r = floor((col + 1/2) / N) in FP32 is exact: the quotient sits at least 1/(2N)
+    // from an integer and col < 2^16.  Padding entries (col 0, value 0) stay in range.
+    const float inv_n = rot_n > 0 ? 1.0f / static_cast<float>(rot_n) : 0.0f;
+    auto rot = [&](uint32_t c) -> uint32_t {
+        if (rot_n <= 0) return c;
+        const uint32_t r = static_cast<uint32_t>((static_cast<float>(c) + 0.5f) * inv_n);
+        const uint32_t cc = c - r * static_cast<uint32_t>(rot_n);
+        return cc * static_cast<uint32_t>(rot_n) + (static_cast<uint32_t>(rot_n) - 1u - r);
+    };
     float acc = 0.0f;
     int k = k0 + gl * kChunk;
     for (; k + G * kChunk < k1; k += 2 * G * kChunk) {
@@ -219,7 +229,7 @@ __device__ __forceinline__ float gather_dot_group(const IT *__restrict__ col,
         load_vals8<VT>(val, k, v);
         load_vals8<VT>(val, k + G * kChunk, v + 8);
 #pragma unroll
-        for (int t = 0; t < 16; ++t) xv[t] = buf_load(xr, 4u * c[t], 0u);
+        for (int t = 0; t < 16; ++t) xv[t] = buf_load(xr, 4u * rot(c[t]), 0u);
 #pragma unroll
         for (int t = 0; t < 16; ++t) acc = fmaf(v[t], xv[t], acc);
     }
@@ -229,7 +239,7 @@ __device__ __forceinline__ float gather_dot_group(const IT *__restrict__ col,
         load_cols8<IT>(col, k, c);
         load_vals8<VT>(val, k, v);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) xv[t] = buf_load(xr, 4u * c[t], 0u);
+        for (int t = 0; t < 8; ++t) xv[t] = buf_load(xr, 4u * rot(c[t]), 0u);
 #pragma unroll
         for (int t = 0; t < 8; ++t) acc = fmaf(v[t], xv[t], acc);
     }
@@ -271,8 +281,13 @@ __global__ __launch_bounds__(256) void k_fwd_single(FwdArgs a) {
     const IT *__restrict__ col = static_cast<const IT *>(a.col);
     const auto xr = make_rsrc(a.x, 4u * static_cast<uint32_t>(a.n_x));
     float acc = 0.0f;
-    if (row < a.m)
-        acc = gather_dot_group<IT, VT, G>(col, a.val, xr, a.row_ptr[row], a.row_ptr[row + 1], gl);
+    if (row < a.m) {
+        // half-stored matrix: the second half of the rows are the first half turned by 90 degrees
+        const bool turned = a.sym_half > 0 && row >= a.sym_half;
+        const int srow = turned ? row - a.sym_half : row;
+        acc = gather_dot_group<IT, VT, G>(col, a.val, xr, a.row_ptr[srow], a.row_ptr[srow + 1], gl,
+                                          turned ? a.img_n : 0);
+    }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (row < a.m && gl == 0) {
@@ -445,6 +460,12 @@ __global__ __launch_bounds__(16 * G) void k_step_single(StepArgs a) {
             } else {
                 const auto er = make_rsrc(a.e, 4u * static_cast<uint32_t>(a.m));
                 acc = gather_dot_group<IT, VT, G>(col, a.val, er, a.row_ptr[j], a.row_ptr[j + 1], gl);
+                if (a.sym_half > 0) {
+                    // the turned rays i + sym_half meet pixel j where ray i meets rho^{-1}(j)
+                    const int jr = (N - 1 - cp) * N + rp;
+                    const auto er2 = make_rsrc(a.e + a.sym_half, 4u * static_cast<uint32_t>(a.m - a.sym_half));
+                    acc += gather_dot_group<IT, VT, G>(col, a.val, er2, a.row_ptr[jr], a.row_ptr[jr + 1], gl);
+                }
             }
         }
 #pragma unroll

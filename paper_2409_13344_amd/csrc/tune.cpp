@@ -127,7 +127,7 @@ appga_status tune_matrix(appga_ctx *ctx, appga_matrix *mat, int flags, appga_tun
             const FwdArgs fa = fwd_args(1);
             for (int g : groups) {
                 double us = 0.0;
-                e = time_us(st, [&] { return launch_forward(mat->A, fa, g, st); }, &us);
+                e = time_us(st, [&] { return launch_forward_single(mat, fa, g, st); }, &us);
                 if (e != hipSuccess) break;
                 if (us < best) {
                     best = us;
@@ -141,7 +141,7 @@ appga_status tune_matrix(appga_ctx *ctx, appga_matrix *mat, int flags, appga_tun
             const StepArgs sa = back_args(1);
             for (int g : groups) {
                 double us = 0.0;
-                e = time_us(st, [&] { return launch_step(mat->AT, sa, g, st); }, &us);
+                e = time_us(st, [&] { return launch_step_mat(mat, sa, g, st); }, &us);
                 if (e != hipSuccess) break;
                 if (us < best) {
                     best = us;
