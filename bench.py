@@ -41,15 +41,15 @@ KERNELS_SRC = os.path.join(ROOT, "paper_2409_13344_amd", "csrc", "kernels.hip")
 # scaled by what the same counters read for a 1 GiB device copy (reads x2.00, writes
 # x1.00).  Valid only for the kernel source it was taken on (sha256 prefix below).
 MEASURED_TRAFFIC = {
-    "kernels_sha256_16": "9c0cbcbd76da6a13",
+    "kernels_sha256_16": "c215b92a6165e038",
     "storage": "bf16",
     "read_scale": 2.0,
     "write_scale": 1.0,
-    "fwd_tiles": {"fetch_kib": 46002.0, "write_kib": 8558.8},
-    "back_tiles": {"fetch_kib": 28267.1, "write_kib": 8192.0},
-    "step_batch": {"fetch_kib": 10490.5, "write_kib": 9216.0},
-    "afppa_primal": {"fetch_kib": 21556.3, "write_kib": 13568.0},
-    "afppa_dual": {"fetch_kib": 27175.1, "write_kib": 49160.0},
+    "fwd_tiles": {"fetch_kib": 46018.2, "write_kib": 8571.8},
+    "back_tiles": {"fetch_kib": 28273.1, "write_kib": 8192.0},
+    "step_batch": {"fetch_kib": 8576.5, "write_kib": 9216.0},
+    "afppa_primal": {"fetch_kib": 21544.6, "write_kib": 13568.0},
+    "afppa_dual": {"fetch_kib": 27151.3, "write_kib": 49160.0},
 }
 
 
