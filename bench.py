@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--afppa-steps", type=int, default=200,
                     help="timed AFPPA-GN steps on the same workload (0 = skip the leg)")
     ap.add_argument("--afppa-cpu-iters", type=int, default=100)
+    ap.add_argument("--c4-steps", type=int, default=50,
+                    help="timed batched steps at 256^2 x 47 with the FP32 matrix (0 = skip)")
     ap.add_argument("--factored-steps", type=int, default=100,
                     help="timed APPGA steps with the factored model (PSF, attenuation, scatter/randoms)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -95,6 +97,23 @@ def parse():
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def timed_pass(ap, torch, ctx, fn):
+    """Kernel times of the launches inside fn() alone: the library's timers are cumulative
+    per context, so the totals before the pass are subtracted."""
+    before = ap.appga_kernel_times(ctx)
+    ap.appga_set_kernel_timing(ctx, True)
+    fn()
+    torch.cuda.synchronize()
+    after = ap.appga_kernel_times(ctx)
+    ap.appga_set_kernel_timing(ctx, False)
+    out = {}
+    for k, v in after.items():
+        b = before.get(k, {"total_ms": 0.0, "count": 0})
+        if v["count"] > b["count"]:
+            out[k] = dict(total_ms=v["total_ms"] - b["total_ms"], count=v["count"] - b["count"])
+    return out
 
 
 def kernel_bytes(kind: str, nnz: int, m: int, d: int, B: int, s_val: int, s_idx: int) -> int:
@@ -137,12 +156,8 @@ def afppa_leg(ap, torch, ctx, mat, pr, g_t, stream, args, s_val, s_idx):
         ap.appga_solve_step(sess, 1)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ap.appga_set_kernel_timing(ctx, True)
-    for _ in range(max(10, min(args.afppa_steps, 100))):
-        ap.appga_solve_step(sess, 1)
-    torch.cuda.synchronize()
-    times = ap.appga_kernel_times(ctx)
-    ap.appga_set_kernel_timing(ctx, False)
+    times = timed_pass(ap, torch, ctx,
+                       lambda: [ap.appga_solve_step(sess, 1) for _ in range(max(10, min(args.afppa_steps, 100)))])
     out_t = torch.empty((B, d), dtype=torch.float32, device=g_t.device)
     stats = ap.appga_solve_end(sess, out_t, B)
     kernels = {}
@@ -192,12 +207,8 @@ def factored_leg(ap, torch, ctx, args, stream):
             ap.appga_solve_step(sess, 1)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        ap.appga_set_kernel_timing(ctx, True)
-        for _ in range(max(10, min(args.factored_steps, 100))):
-            ap.appga_solve_step(sess, 1)
-        torch.cuda.synchronize()
-        times = ap.appga_kernel_times(ctx)
-        ap.appga_set_kernel_timing(ctx, False)
+        times = timed_pass(ap, torch, ctx,
+                           lambda: [ap.appga_solve_step(sess, 1) for _ in range(max(10, min(args.factored_steps, 100)))])
         out_t = torch.empty((B, d), dtype=torch.float32, device=dev)
         stats = ap.appga_solve_end(sess, out_t, B)
     finally:
@@ -221,6 +232,42 @@ def factored_leg(ap, torch, ctx, args, stream):
                 model="A = diag(att) G H: PSF FWHM %.2f px (R = %d), water attenuation, per-bin "
                       "scatter + randoms background" % (pp.fwhm_px, psf_R),
                 kernels=kernels, objective_lane0=stats[0]["objective"])
+
+
+def c4_leg(ap, torch, ctx, pr, mat, steps: int):
+    """Batched APPGA at C4 size: 47 lanes of the 256 x 256 / 256 bins x 252 angles geometry with
+    the FP32 matrix (about 320 MB for A and its transpose, above the 256 MB Infinity Cache).  The
+    lanes reuse the leg's 8 sinograms in turn (timing does not depend on the data values)."""
+    geom = pr.geom
+    B = 47
+    idx = [b % len(pr.seeds) for b in range(B)]
+    g_t = torch.as_tensor(np.ascontiguousarray(pr.g[idx])).cuda()
+    params = [ap.make_params(lam=0.01, eps=1e-3, omega=1.0, iterations=1000,
+                             gamma_scalar=float(pr.gamma[i][0])) for i in idx]
+    s = ap.appga_solve_begin(ctx, mat, g_t, None, params, None, torch.cuda.current_stream().cuda_stream)
+    for _ in range(5):
+        ap.appga_solve_step(s, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ap.appga_solve_step(s, 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    times = timed_pass(ap, torch, ctx, lambda: [ap.appga_solve_step(s, 1) for _ in range(max(10, steps // 2))])
+    ap.appga_solve_end(s, torch.empty((B, geom.d), dtype=torch.float32, device="cuda"), B)
+    nnz, m, d = pr.A.nnz, geom.m, geom.d
+    kernels = {}
+    for name, kind in (("fwd_tiles", "forward"), ("back_tiles", "back"), ("step_batch", "update")):
+        t = times.get(name)
+        if not t or t["count"] == 0:
+            continue
+        avg_ms = t["total_ms"] / t["count"]
+        nb = kernel_bytes(kind, nnz, m, d, B, 4, 2)
+        gbs = nb / (avg_ms * 1e-3) / 1e9
+        kernels[name] = dict(avg_us=round(1e3 * avg_ms, 2), bytes=nb, gbs=round(gbs, 1),
+                             frac=round(gbs / HBM_PEAK_GBS, 4))
+    return dict(value=round(B * steps / dt, 1), unit="solve-iterations/s", ms_per_step=round(1e3 * dt / steps, 4),
+                steps=steps, solves=B, matrix="FP32, nnz %d" % nnz, kernels=kernels)
 
 
 def cpu_baseline_afppa(pr, n_iters: int):
@@ -327,12 +374,7 @@ def projector_leg(ap, torch, ctx, pr, mat, steps: int):
     for _ in range(5):
         ap.appga_solve_step(s, 1)
     torch.cuda.synchronize()
-    ap.appga_set_kernel_timing(ctx, True)
-    for _ in range(steps):
-        ap.appga_solve_step(s, 1)
-    torch.cuda.synchronize()
-    times = ap.appga_kernel_times(ctx)
-    ap.appga_set_kernel_timing(ctx, False)
+    times = timed_pass(ap, torch, ctx, lambda: [ap.appga_solve_step(s, 1) for _ in range(steps)])
     ap.appga_solve_end(s, torch.empty((1, geom.d), dtype=torch.float32, device="cuda"), 1)
     nnz, m, d = pr.A.nnz, geom.m, geom.d
     out = {}
@@ -403,13 +445,8 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
 
     # kernel durations from HIP events on the launch stream (separate pass)
-    ap.appga_set_kernel_timing(ctx, True)
     n_prof = max(10, min(args.steps, 100))
-    for _ in range(n_prof):
-        ap.appga_solve_step(sess, 1)
-    torch.cuda.synchronize()
-    times = ap.appga_kernel_times(ctx)
-    ap.appga_set_kernel_timing(ctx, False)
+    times = timed_pass(ap, torch, ctx, lambda: [ap.appga_solve_step(sess, 1) for _ in range(n_prof)])
     out_t = torch.empty((B, d), dtype=torch.float32, device=dev)
     stats = ap.appga_solve_end(sess, out_t, B)
     s_val = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}[args.storage]
@@ -490,6 +527,10 @@ def main():
         projector = projector_leg(ap, torch, ctx, pr256, mat256, max(20, min(args.steps, 100)))
         t256 = ap.appga_tune(ctx, mat256, ap.APPGA_TUNE_SINGLE)
         projector["lanes_per_row"] = {"forward": t256["group_fwd"], "back": t256["group_back"]}
+    c4 = None
+    if not args.no_projector and args.c4_steps > 0:
+        log("batched C4 leg (256^2 x 47, FP32 matrix)")
+        c4 = c4_leg(ap, torch, ctx, pr256, mat256, args.c4_steps)
 
     serving = None
     if args.serve_requests > 0 and not args.profile:
@@ -546,6 +587,7 @@ def main():
         "factored": factored,
         "serving": serving,
         "projector_single_256": projector,
+        "batched_c4_256x47": c4,
         "matrix_bytes": info,
         "tile_forms": tinfo,
         "tuning": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tuning.items()},
