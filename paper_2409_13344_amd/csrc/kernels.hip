@@ -337,11 +337,13 @@ __global__ __launch_bounds__(256) void k_fwd_batch(FwdArgs a) {
 // in LDS) and f on the 8 x 8 block around it.
 // ------------------------------------------------------------------------
 
-// The six components at (r, c) (0 <= r, c < N); F(r, c) reads the image.
-template <typename Fn>
+// The six components at (r, c) (0 <= r, c < N); F(r, c) reads the image.  IN
+// asserts that (r, c) is at least one pixel away from every edge, which makes
+// every boundary condition true at compile time.
+template <bool IN = false, typename Fn>
 __device__ __forceinline__ void uv6(const Fn &F, int r, int c, int N, float o[6]) {
     const float f00 = F(r, c);
-    const bool cl = c >= 1, cr = c <= N - 2, ru = r >= 1, rd = r <= N - 2;
+    const bool cl = IN || c >= 1, cr = IN || c <= N - 2, ru = IN || r >= 1, rd = IN || r <= N - 2;
     const float fl = cl ? F(r, c - 1) : 0.0f;
     const float fr = cr ? F(r, c + 1) : 0.0f;
     const float fu = ru ? F(r - 1, c) : 0.0f;
@@ -362,10 +364,10 @@ __device__ __forceinline__ void uv6(const Fn &F, int r, int c, int N, float o[6]
 }
 
 // Weighted vector (w1 u1, w1 u2, w2 v1..v4) at (r, c).
-template <typename Fn>
+template <bool IN = false, typename Fn>
 __device__ __forceinline__ void pq6(const Fn &F, int r, int c, int N, float l1, float l2, float eps,
                                     float o[6]) {
-    uv6(F, r, c, N, o);
+    uv6<IN>(F, r, c, N, o);
     const float n1 = sqrtf(o[0] * o[0] + o[1] * o[1]);
     const float n2 = sqrtf(o[2] * o[2] + o[3] * o[3] + o[4] * o[4] + o[5] * o[5]);
     const float w1 = l1 / fmaxf(n1, eps);
@@ -375,10 +377,10 @@ __device__ __forceinline__ void pq6(const Fn &F, int r, int c, int N, float l1, 
 }
 
 // grad R at (r, c) from the weighted vectors; Q(dr, dc, k) reads component k
-// at (r + dr, c + dc) (only in-image positions are read).
-template <typename Qf>
+// at (r + dr, c + dc) (only in-image positions are read); IN as for uv6.
+template <bool IN = false, typename Qf>
 __device__ __forceinline__ float combine_grad(const Qf &Q, int r, int c, int N) {
-    const bool cl = c >= 1, cr = c <= N - 2, ru = r >= 1, rd = r <= N - 2;
+    const bool cl = IN || c >= 1, cr = IN || c <= N - 2, ru = IN || r >= 1, rd = IN || r <= N - 2;
     // (I (x) D^T) p1 and (D^T (x) I) p2
     float g = (cl ? Q(0, 0, 0) : 0.0f) - (cr ? Q(0, 1, 0) : 0.0f);
     g += (ru ? Q(0, 0, 1) : 0.0f) - (rd ? Q(1, 0, 1) : 0.0f);
@@ -532,7 +534,9 @@ __global__ __launch_bounds__(16 * G) void k_step_single(StepArgs a) {
 // waves, lanes = the 64 solves of chunk blockIdx.y: wave w back-projects pixel
 // w; the 8 x 8 halo of f~ is staged in LDS; the 36 weighted vectors of the
 // 6 x 6 block are computed once (waves 0..15 take positions w, w+16, w+32) and
-// kept in LDS; wave w combines them for pixel w and applies the update.
+// kept in LDS; wave w combines them for pixel w and applies the update.  Tiles
+// whose halo lies inside the image (all but the outer ring) take a copy of the
+// stencil code with the boundary conditions removed at compile time.
 // ------------------------------------------------------------------------
 
 template <int VT>
@@ -573,21 +577,37 @@ __global__ __launch_bounds__(1024, 8) void k_step_batch(StepArgs a) {
         const auto vr = make_rsrc(a.val, static_cast<uint32_t>(a.nnz_padded) * vbytes<VT>());
         gF = gather_dot_lanes64<VT>(cr, vr, er, a.row_ptr[j], a.row_ptr[j + 1], 4u * lane);
     }
-    for (int q = w; q < 64; q += 16) {
+    // the 8 x 8 halo inside the image: every stencil position of the tile is interior
+    const bool interior = r0 >= 2 && c0 >= 2 && r0 + 6 <= N && c0 + 6 <= N;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int q = w + 16 * k;
         const int hr = r0 - 2 + (q >> 3), hc = c0 - 2 + (q & 7);
-        halo[q][lane] = (hr >= 0 && hr < N && hc >= 0 && hc < N)
+        halo[q][lane] = (interior || (hr >= 0 && hr < N && hc >= 0 && hc < N))
                             ? a.ft[vbase + static_cast<size_t>(hr * N + hc) * 64]
                             : 0.0f;
     }
     __syncthreads();
     const LaneParams lp = a.lp[b];
     auto F = [&](int rr, int cc) { return halo[(rr - r0 + 2) * 8 + (cc - c0 + 2)][lane]; };
-    for (int q = w; q < 36; q += 16) {
-        const int rr = r0 - 1 + q / 6, cc = c0 - 1 + q % 6;
-        float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (rr >= 0 && rr < N && cc >= 0 && cc < N) pq6(F, rr, cc, N, lp.lambda1, lp.lambda2, lp.eps, o);
+    auto weighted = [&](auto in_tag) {
+        constexpr bool IN = decltype(in_tag)::value;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) pqs[k][q][lane] = o[k];
+        for (int k = 0; k < 3; ++k) {
+            const int q = w + 16 * k;
+            if (q >= 36) break;
+            const int rr = r0 - 1 + q / 6, cc = c0 - 1 + q % 6;
+            float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (IN || (rr >= 0 && rr < N && cc >= 0 && cc < N))
+                pq6<IN>(F, rr, cc, N, lp.lambda1, lp.lambda2, lp.eps, o);
+#pragma unroll
+            for (int t = 0; t < 6; ++t) pqs[t][q][lane] = o[t];
+        }
+    };
+    if (interior) {
+        weighted(std::true_type{});
+    } else {
+        weighted(std::false_type{});
     }
     __syncthreads();
     const float ftc = in ? F(r, c) : 0.0f;
@@ -600,7 +620,7 @@ __global__ __launch_bounds__(1024, 8) void k_step_batch(StepArgs a) {
         if (a.out_mode == SO_BACK) {
             a.out[o] = gF;
         } else {
-            const float gR = combine_grad(Q, r, c, N);
+            const float gR = interior ? combine_grad<true>(Q, r, c, N) : combine_grad(Q, r, c, N);
             if (a.out_mode == SO_REG) {
                 a.out[o] = gR;
             } else {
@@ -622,16 +642,11 @@ __global__ __launch_bounds__(1024, 8) void k_step_batch(StepArgs a) {
         red[(w * 64 + lane) * 2] = dd;
         red[(w * 64 + lane) * 2 + 1] = nn;
         __syncthreads();
-        if (w == 0 && act) {
-            double s0 = 0.0, s1 = 0.0;
+        if (w < 2 && act) {   // wave 0 sums |f^{k+1} - f^k|^2, wave 1 |f^{k+1}|^2
+            double s = 0.0;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                s0 += red[(q * 64 + lane) * 2];
-                s1 += red[(q * 64 + lane) * 2 + 1];
-            }
-            const size_t po = (static_cast<size_t>(blockIdx.x) * a.Bp + b) * 2;
-            a.re_part[po] = s0;
-            a.re_part[po + 1] = s1;
+            for (int q = 0; q < 16; ++q) s += red[(q * 64 + lane) * 2 + w];
+            a.re_part[(static_cast<size_t>(blockIdx.x) * a.Bp + b) * 2 + w] = s;
         }
     }
 }
