@@ -395,7 +395,7 @@ def projector_leg(ap, torch, ctx, pr, mat, steps: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (independent solves "
+        print("bench.py measures one GPU: the library has no multi-GPU path (independent solves "
               "would shard across GPUs with no communication); run with --gpus 1", flush=True)
         sys.exit(2)
     import torch
