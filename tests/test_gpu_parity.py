@@ -371,11 +371,16 @@ def test_reduced_precision_single(ctx, c2, storage):
     assert e_q <= 1e-5
 
 
-def test_c4_sampled_slices(ctx):
+@pytest.fixture(scope="module")
+def c4():
+    return synth.config_problem("c4_256x47")
+
+
+def test_c4_sampled_slices(ctx, c4):
     """256^2 x 47 slices sharing the 256 x 252 matrix, omega = 1, 200 iterations, FP32 matrix:
     two sampled slices against the oracle."""
     say("C4 fp32 sampled")
-    pr = synth.config_problem("c4_256x47")
+    pr = c4
     mat = ap.load_matrix(ctx, pr.A, pr.geom, "f32")
     try:
         params = [ap.make_params(lam=0.01, eps=1e-3, omega=1.0, iterations=200)] * 47
@@ -387,6 +392,43 @@ def test_c4_sampled_slices(ctx):
         err = rel_l2(f[b], ref)
         say("  slice %d rel L2 %.3e" % (b, err))
         assert err <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+def test_c4_reduced_precision(ctx, c4, storage):
+    """C4 (256^2 x 47 slices, omega = 1, 200 iterations) with the matrix stored in BF16 or
+    FP8 with row scales: slices 0 and 46 against the oracle on the dequantised matrix
+    (parity, floor-aware) and on the exact matrix (reported, loose bound)."""
+    say("C4 %s sampled" % storage)
+    pr = c4
+    mat = ap.load_matrix(ctx, pr.A, pr.geom, storage)
+    try:
+        deq = ap.appga_matrix_dequantized(mat, pr.A.nnz)
+        params = [ap.make_params(lam=0.01, eps=1e-3, omega=1.0, iterations=200)] * 47
+        f, stats = ap.appga_reconstruct_batch(ctx, mat, pr.geom.d, pr.g, pr.gamma, params)
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    Aq = copy.copy(pr.A)
+    Aq.val = deq
+    bound_exact = {"bf16": 2e-2, "fp8": 2e-1}[storage]
+    run = lambda A, g, b: oracle.appga(A, 256, 252, g, pr.gamma[b], 0.01, 0.01, 1e-3, 1.0, 200)["f"]
+    jobs = []
+    for b in (0, 46):
+        g = pr.g[b].astype(np.float64)
+        pert = g * (1.0 + 1e-7 * np.random.default_rng(b).standard_normal(g.shape))
+        jobs += [(Aq, g, b), (pr.A, g, b), (Aq, pert, b)]
+    with ThreadPoolExecutor(6) as ex:
+        res = list(ex.map(lambda j: run(*j), jobs))
+    for i, b in enumerate((0, 46)):
+        ref_q, ref_x, pert_q = res[3 * i:3 * i + 3]
+        floor = rel_l2(pert_q, ref_q)
+        e_q, e_x = rel_l2(f[b], ref_q), rel_l2(f[b], ref_x)
+        tol = max(1e-5, 4.0 * floor)
+        say("  slice %d: vs dequantised-matrix oracle %.3e (floor %.2e, tol %.2e), vs exact-matrix "
+            "oracle %.3e" % (b, e_q, floor, tol, e_x))
+        assert e_q <= tol
+        assert e_x <= bound_exact
+        assert stats[b]["guard_clamps"] == 0
 
 
 # --------------------------------------------------------- error paths ---
