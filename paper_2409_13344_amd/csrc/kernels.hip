@@ -1534,12 +1534,91 @@ __global__ __launch_bounds__(256) void k_psf_pass(const float *in, int n_parts, 
     out[base + (LANES ? static_cast<size_t>(j) * 64 : static_cast<size_t>(j))] = acc;
 }
 
+// The same pass for the lane layout with a radius R known at compile time: a
+// thread takes a run of P consecutive pixels along the pass's axis for one
+// solve, holds the P + 2R inputs they need in registers (indices clamped into
+// the image, as above) and forms each output from them with the same weights
+// in the same order, so the results equal k_psf_pass's.  Each input is loaded
+// once per run instead of once per output, and a wave keeps P + 2R loads in
+// flight.
+template <int SPLIT, int R, int P>
+__global__ __launch_bounds__(256) void k_psf_run(const float *in, float *out, int n, int Bp, int axis,
+                                                 const float *taps) {
+    const int d = n * n;
+    const int runs = (n + P - 1) / P;
+    const int u = blockIdx.x * 256 + threadIdx.x;
+    if (u >= n * runs * 64) return;
+    const int s = u >> 6;
+    const int line = s / runs, p0 = (s - line * runs) * P;
+    const size_t base = static_cast<size_t>(blockIdx.y) * d * 64 + (u & 63);
+    const size_t stride = static_cast<size_t>(d) * Bp;
+    auto at = [&](int q) {   // vector index of position q of this line
+        const int jj = axis == 0 ? line * n + q : q * n + line;
+        return base + static_cast<size_t>(jj) * 64;
+    };
+    float w[2 * R + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) w[k] = taps[k];
+    float v[P + 2 * R];
+#pragma unroll
+    for (int t = 0; t < P + 2 * R; ++t) {
+        const int qc = min(max(p0 + t - R, 0), n - 1);
+        const size_t o = at(qc);
+        float x = in[o];
+        if (SPLIT == 2) x += in[stride + o];
+        v[t] = x;
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        if (p0 + i >= n) break;
+        float acc = 0.0f;
+#pragma unroll
+        for (int k = 0; k <= 2 * R; ++k) {
+            const int q = p0 + i + k - R;
+            acc = fmaf((q >= 0 && q < n) ? w[k] : 0.0f, v[i + k], acc);
+        }
+        out[at(p0 + i)] = acc;
+    }
+}
+
+// Run length of k_psf_run (8 measured a little faster than 4 at 128^2 x 64).
+constexpr int kPsfRun = 8;
+
+template <int SPLIT>
+static hipError_t launch_psf_run(const float *in, float *out, int n, int Bp, int axis, const float *taps, int R,
+                                 hipStream_t st) {
+    constexpr int P = kPsfRun;
+    const int runs = (n + P - 1) / P;
+    const dim3 grid((n * runs * 64 + 255) / 256, Bp / 64), block(256);
+    switch (R) {
+#define APPGA_PSF_RUN_CASE(RR)                                                                               \
+    case RR:                                                                                                  \
+        hipLaunchKernelGGL((k_psf_run<SPLIT, RR, P>), grid, block, 0, st, in, out, n, Bp, axis, taps);        \
+        break;
+        APPGA_PSF_RUN_CASE(1)
+        APPGA_PSF_RUN_CASE(2)
+        APPGA_PSF_RUN_CASE(3)
+        APPGA_PSF_RUN_CASE(4)
+        APPGA_PSF_RUN_CASE(5)
+        APPGA_PSF_RUN_CASE(6)
+        APPGA_PSF_RUN_CASE(7)
+        APPGA_PSF_RUN_CASE(8)
+#undef APPGA_PSF_RUN_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_psf_pass(const float *in, int n_parts, float *out, int n, int B, int Bp, int axis,
                            const float *taps, int R, hipStream_t st) {
     (void)B;
     if (R < 0 || 2 * R + 1 > kPsfMaxTaps || n_parts < 1 || (Bp != 1 && Bp % 64 != 0)) return hipErrorInvalidValue;
     const int d = n * n;
     const dim3 block(256);
+    if (Bp != 1 && R >= 1 && R <= 8 && n_parts <= 2)
+        return n_parts == 1 ? launch_psf_run<1>(in, out, n, Bp, axis, taps, R, st)
+                            : launch_psf_run<2>(in, out, n, Bp, axis, taps, R, st);
     if (Bp == 1) {
         const dim3 grid((d + 255) / 256, 1);
         if (n_parts == 1)

@@ -92,6 +92,45 @@ def test_operators_128(ctx, p128, B):
         assert err.max() <= 4e-6 and errb.max() <= 4e-6
 
 
+@pytest.mark.parametrize("fwhm", [5.5, 9.0])
+def test_operators_wide_psf(ctx, fwhm):
+    """Wider PSFs in the lane layout: R = 8 (the largest radius the run kernel takes) and
+    R = 12 (the per-output kernel), 64 solves on a 45^2 image (runs of 8 pixels end ragged),
+    forward and back operators against the oracle's pieces."""
+    geom = synth.Geometry(45, 64, 60)
+    pp = synth.make_physics_problem(geom, [21], tc=3e5, fov_mm=45 * 2.34, G=synth.cached_matrix(geom))
+    R = oracle.psf_radius(fwhm)
+    say("factored operators 45^2, FWHM %.1f px (R = %d), B = 64" % (fwhm, R))
+    G = pp.G
+    mat = ap.appga_load_system_matrix_factored(ctx, geom.n, geom.n_angles, geom.n_bins, G.row_ptr, G.col, G.val,
+                                               "f32", row_factors=pp.att, psf_fwhm_px=fwhm)
+    try:
+        assert ap.appga_matrix_psf(mat)[1] == R
+        rng = np.random.default_rng(int(fwhm * 10))
+        B = 64
+        x = rng.uniform(0.0, 2.0, (B, geom.d)).astype(np.float32)
+        gam = rng.uniform(0.5, 1.5, (B, geom.m)).astype(np.float32)
+        r = rng.standard_normal((B, geom.m)).astype(np.float32)
+        y_t = torch.empty((B, geom.m), dtype=torch.float32, device="cuda")
+        b_t = torch.empty((B, geom.d), dtype=torch.float32, device="cuda")
+        ap.appga_op_forward(ctx, mat, torch.as_tensor(x).cuda(), torch.as_tensor(gam).cuda(), y_t)
+        ap.appga_op_back(ctx, mat, torch.as_tensor(r).cuda(), b_t)
+        y, bk = y_t.cpu().numpy(), b_t.cpu().numpy()
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    absG = synth.SparseMatrix(G.n_rows, G.n_cols, G.row_ptr, G.col, np.abs(G.val))
+    for b in (0, 31, 63):
+        xb = x[b].astype(np.float64)
+        ref = pp.att * oracle.forward(G, oracle.psf_apply(geom.n, fwhm, xb)) + gam[b]
+        mag = pp.att * oracle.forward(absG, oracle.psf_apply(geom.n, fwhm, np.abs(xb))) + gam[b]
+        refb = oracle.psf_apply(geom.n, fwhm, oracle.back(G, pp.att * r[b]))
+        magb = oracle.psf_apply(geom.n, fwhm, oracle.back(absG, pp.att * np.abs(r[b])))
+        err = (np.abs(y[b] - ref) / mag).max()
+        errb = (np.abs(bk[b] - refb) / np.maximum(magb, 1e-30)).max()
+        say("  solve %d: forward max rel %.2e, back max rel %.2e" % (b, err, errb))
+        assert err <= 4e-6 and errb <= 4e-6
+
+
 @pytest.fixture(scope="module")
 def small():
     geom = synth.Geometry(32, 48, 40)
