@@ -1018,10 +1018,7 @@ namespace appga {
 
 hipError_t psf_blur(const appga_matrix *mat, const float *in, int n_parts, float *tmp, float *out, int B, int Bp,
                     hipStream_t st) {
-    const int n = mat->geom.n;
-    hipError_t he = launch_psf_pass(in, n_parts, tmp, n, B, Bp, 0, mat->psf_taps, mat->psf_R, st);
-    if (he == hipSuccess) he = launch_psf_pass(tmp, 1, out, n, B, Bp, 1, mat->psf_taps, mat->psf_R, st);
-    return he;
+    return launch_psf_blur(in, n_parts, tmp, out, mat->geom.n, B, Bp, mat->psf_taps, mat->psf_R, st);
 }
 
 static appga_status sess_alloc(appga_solve *s) {

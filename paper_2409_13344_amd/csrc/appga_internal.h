@@ -235,6 +235,11 @@ struct AfppaArgs {
 constexpr int kPsfMaxTaps = 65;
 hipError_t launch_psf_pass(const float *in, int n_parts, float *out, int n, int B, int Bp, int axis,
                            const float *taps, int R, hipStream_t st);
+// H applied to the sum of n_parts partial sums: the pass along axis 0 into tmp,
+// then along axis 1 into out; for batches with R <= 4 both passes run in one
+// launch with the same arithmetic (tmp unused).
+hipError_t launch_psf_blur(const float *in, int n_parts, float *tmp, float *out, int n, int B, int Bp,
+                           const float *taps, int R, hipStream_t st);
 
 constexpr int kAfppaPmSlots = 32;
 

@@ -1610,6 +1610,101 @@ static hipError_t launch_psf_run(const float *in, float *out, int n, int Bp, int
     return hipGetLastError();
 }
 
+// Both passes of the blur in one launch, for the lane layout with R <= 4 known
+// at compile time (wider PSFs take k_psf_run twice: their register windows
+// would not fit a 1024-thread workgroup).  A workgroup takes an 8 x 8 tile of
+// pixels for the 64 solves of chunk blockIdx.y.  Pass 1 (along c): wave w
+// takes row w of the tile's 8 + 2R rows (image rows clamped as in
+// k_psf_pass), loads its 8 + 2R inputs once and writes its 8 partial outputs
+// to LDS.  Pass 2
+// (along r): wave w < 8 takes column w of the tile and forms its outputs from
+// the 8 + 2R LDS rows they need.  Each LDS row t holds pass 1's result for
+// image row clamp(r0 - R + t), the value the second launch of the two-pass
+// form reads, and weights and order are those of the two launches, so the
+// results are equal; the intermediate image never leaves the CU.
+template <int SPLIT, int R>
+__global__ __launch_bounds__(1024) void k_psf_2d(const float *in, float *out, int n, int Bp, const float *taps) {
+    constexpr int T = 8, ROWS = T + 2 * R;
+    static_assert(ROWS <= 16, "one row of the tile per wave");
+    __shared__ float mid[ROWS][T][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int d = n * n;
+    const int tiles_x = (n + T - 1) / T;
+    const int r0 = (blockIdx.x / tiles_x) * T, c0 = (blockIdx.x % tiles_x) * T;
+    const size_t base = static_cast<size_t>(blockIdx.y) * d * 64 + lane;
+    const size_t stride = static_cast<size_t>(d) * Bp;
+    float wt[2 * R + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) wt[k] = taps[k];
+    if (w < ROWS) {
+        const int t = w;
+        const int rr = min(max(r0 - R + t, 0), n - 1);
+        float v[T + 2 * R];
+#pragma unroll
+        for (int i = 0; i < T + 2 * R; ++i) {
+            const int qc = min(max(c0 - R + i, 0), n - 1);
+            const size_t o = base + static_cast<size_t>(rr * n + qc) * 64;
+            float x = in[o];
+            if (SPLIT == 2) x += in[stride + o];
+            v[i] = x;
+        }
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k <= 2 * R; ++k) {
+                const int q = c0 + j + k - R;
+                acc = fmaf((q >= 0 && q < n) ? wt[k] : 0.0f, v[j + k], acc);
+            }
+            mid[t][j][lane] = acc;
+        }
+    }
+    __syncthreads();
+    const int c = c0 + w;
+    if (w >= T || c >= n) return;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        const int r = r0 + i;
+        if (r >= n) break;
+        float acc = 0.0f;
+#pragma unroll
+        for (int k = 0; k <= 2 * R; ++k) {
+            const int q = r + k - R;
+            acc = fmaf((q >= 0 && q < n) ? wt[k] : 0.0f, mid[i + k][w][lane], acc);
+        }
+        out[base + static_cast<size_t>(r * n + c) * 64] = acc;
+    }
+}
+
+hipError_t launch_psf_blur(const float *in, int n_parts, float *tmp, float *out, int n, int B, int Bp,
+                           const float *taps, int R, hipStream_t st) {
+    if (Bp != 1 && Bp % 64 == 0 && R >= 1 && R <= 4 && (n_parts == 1 || n_parts == 2)) {
+        const int tiles_x = (n + 7) / 8;
+        const dim3 grid(tiles_x * tiles_x, Bp / 64), block(1024);
+        switch (R * 4 + n_parts) {
+#define APPGA_PSF_2D_CASE(RR)                                                                         \
+    case RR * 4 + 1:                                                                                   \
+        hipLaunchKernelGGL((k_psf_2d<1, RR>), grid, block, 0, st, in, out, n, Bp, taps);               \
+        break;                                                                                         \
+    case RR * 4 + 2:                                                                                   \
+        hipLaunchKernelGGL((k_psf_2d<2, RR>), grid, block, 0, st, in, out, n, Bp, taps);               \
+        break;
+            APPGA_PSF_2D_CASE(1)
+            APPGA_PSF_2D_CASE(2)
+            APPGA_PSF_2D_CASE(3)
+            APPGA_PSF_2D_CASE(4)
+#undef APPGA_PSF_2D_CASE
+            default:
+                return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    hipError_t he = launch_psf_pass(in, n_parts, tmp, n, B, Bp, 0, taps, R, st);
+    if (he == hipSuccess) he = launch_psf_pass(tmp, 1, out, n, B, Bp, 1, taps, R, st);
+    return he;
+}
+
 hipError_t launch_psf_pass(const float *in, int n_parts, float *out, int n, int B, int Bp, int axis,
                            const float *taps, int R, hipStream_t st) {
     (void)B;

@@ -92,11 +92,12 @@ def test_operators_128(ctx, p128, B):
         assert err.max() <= 4e-6 and errb.max() <= 4e-6
 
 
-@pytest.mark.parametrize("fwhm", [5.5, 9.0])
+@pytest.mark.parametrize("fwhm", [1.5, 5.5, 9.0])
 def test_operators_wide_psf(ctx, fwhm):
-    """Wider PSFs in the lane layout: R = 8 (the largest radius the run kernel takes) and
-    R = 12 (the per-output kernel), 64 solves on a 45^2 image (runs of 8 pixels end ragged),
-    forward and back operators against the oracle's pieces."""
+    """Other PSF widths in the lane layout, one for each blur kernel: R = 2 (the one-launch
+    2-D kernel, which takes R <= 4), R = 8 (the largest radius of the run kernel) and R = 12
+    (the per-output kernel). 64 solves on a 45^2 image (tiles and runs of 8 pixels end
+    ragged); forward and back operators against the oracle's pieces."""
     geom = synth.Geometry(45, 64, 60)
     pp = synth.make_physics_problem(geom, [21], tc=3e5, fov_mm=45 * 2.34, G=synth.cached_matrix(geom))
     R = oracle.psf_radius(fwhm)
