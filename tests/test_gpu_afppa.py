@@ -289,6 +289,26 @@ def test_batched_configuration_sampled(ctx):
               pr.g[b], pr.gamma[b])
 
 
+def test_two_chunks_ragged(ctx):
+    """70 solves (two chunks of 64 lanes, the second holding 6) on a 37^2 image (tiles and
+    pixel groups end ragged), FP32 matrix, AFPPA-GN: solves at both ends of each chunk
+    against the oracle."""
+    say("AFPPA 37^2 x 70 (two chunks)")
+    geom = synth.Geometry(37, 56, 48)
+    pr = synth.make_problem(geom, list(range(7000, 7070)), tc_range=(1e5, 1e7), rf_range=(0.05, 0.2))
+    mat = ap.load_matrix(ctx, pr.A, geom, "f32")
+    try:
+        params = [afppa_params(ap.APPGA_MOMENTUM_GN, 0.5, iterations=60)] * 70
+        f, du, st = ap.appga_afppa_batch(ctx, mat, geom.d, pr.g, pr.gamma, params, duals=True)
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    for b in (0, 63, 64, 69):
+        ref, ref_duals, floor_f, floor_y = with_floor(pr.A, 37, 48, pr.g[b], pr.gamma[b], ap.APPGA_MOMENTUM_GN,
+                                                      0.5, 60, seed=b)
+        check("solve %d" % b, f[b], du[b], st[b], ref, ref_duals, floor_f, floor_y, pr.A, 37, pr.g[b],
+              pr.gamma[b])
+
+
 def test_afppa_errors_through_the_abi(ctx, c2, c2_mat):
     say("AFPPA errors")
     d = c2.geom.d

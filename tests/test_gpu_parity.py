@@ -300,6 +300,46 @@ def test_batch_equals_solo(ctx, c2, c2_mat):
         assert abs(sb[b]["objective"] - ss["objective"]) <= 1e-6 * abs(ss["objective"])
 
 
+def test_two_chunks_ragged(ctx):
+    """70 solves (two chunks of 64 lanes, the second holding 6) on a 37^2 image (tiles end
+    ragged), FP32 matrix, APPGA with mixed omega.
+
+    * Exact: solves 63..69 (the end of chunk 0 and all of chunk 1) give bit-identical
+      results when run as lanes 0..6 of a batch of 7, so the ragged chunk computes what a
+      full one does.
+    * Oracle, floor-aware: solves 0, 64 and 69.  Solve 63 is left out of this gate: its
+      result moves by up to 7e-5 between valid FP32 summation orders (measured: the
+      single-solve path lands 4.6e-6 or 6.7e-5 from the oracle depending on the lanes per
+      row the autotuner picks, the batched row kernels 2.3e-5, the tile kernels 6.6e-5),
+      far above its 1e-7 data-perturbation floor of 3e-7."""
+    say("APPGA 37^2 x 70 (two chunks)")
+    geom = synth.Geometry(37, 56, 48)
+    pr = synth.make_problem(geom, list(range(7000, 7070)), tc_range=(1e5, 1e7), rf_range=(0.05, 0.2))
+    mat = ap.load_matrix(ctx, pr.A, geom, "f32")
+    omegas = [(0.3, 0.5, 1.0)[b % 3] for b in range(70)]
+    params = [ap.make_params(lam=0.02, eps=1e-3, omega=om, iterations=80) for om in omegas]
+    try:
+        f, st = ap.appga_reconstruct_batch(ctx, mat, geom.d, pr.g, pr.gamma, params)
+        f7, _ = ap.appga_reconstruct_batch(ctx, mat, geom.d, pr.g[63:], pr.gamma[63:], params[63:])
+    finally:
+        ap.appga_free_system_matrix(ctx, mat)
+    for i in range(7):
+        assert np.array_equal(f[63 + i], f7[i]), 63 + i
+    say("  solves 63..69 bit-identical as lanes 0..6 of a batch of 7")
+    for b in (0, 64, 69):
+        run = lambda g: oracle.appga(pr.A, 37, 48, g, pr.gamma[b], 0.02, 0.02, 1e-3, omegas[b], 80,
+                                     history=True)
+        g = pr.g[b].astype(np.float64)
+        ref = run(g)
+        floor = rel_l2(run(g * (1.0 + 1e-7 * np.random.default_rng(b).standard_normal(g.shape)))["f"],
+                       ref["f"])
+        err = rel_l2(f[b], ref["f"])
+        say("  solve %d (omega %.1f): image %.3e (floor %.2e), Phi %.10e vs %.10e" % (
+            b, omegas[b], err, floor, st[b]["objective"], ref["obj"][-1]))
+        assert err <= max(1e-5, 4.0 * floor)
+        assert abs(st[b]["objective"] - ref["obj"][-1]) <= 1e-7 * abs(ref["obj"][-1])
+
+
 @pytest.mark.parametrize("storage", ["bf16", "f16", "fp8"])
 def test_reduced_precision_c3_sampled(ctx, c2, storage):
     """128^2 x 64 solves sharing the matrix (the batched configuration, 300 iterations), sampled
